@@ -1,0 +1,197 @@
+/*
+ * libhevmc — Metropolis sweeps and local energies of Jastrow variational Monte
+ * Carlo for liquid 4He on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Y. Lutsyshyn, "Fast quantum Monte Carlo on a GPU", arXiv:1312.1282.
+ *   - wavefunction psi = exp(sum_{i<j} u(r_ij))                      Sec. 2, Eq. (6)
+ *   - u(r) = f(r) + f(L-r) - 2 f(L/2) for r <= L/2, 0 beyond,
+ *     f(r) = -(1/2)(b/r)^5   (multiplicative reading of Eq. (8))    Sec. 2, Eqs. (8), (9)
+ *   - V(r) = HFD-B(HE) ("Aziz-II"), truncated at L/2               Sec. 2, Sec. 7
+ *   - single-particle Gaussian moves, acceptance exp(2 dU) > xi,
+ *     dU = sum_{i != s} [u(|r_s'-r_i|) - u(|r_s-r_i|)]              Sec. 2, Eqs. (5), (7)
+ *   - local energy E_L = V + T, with T_PB, T_JF, T_F estimators      Sec. 2, Sec. 5.4
+ *   - minimum-image periodic cubic box of side L = (N/density)^(1/3) Sec. 5.1, Sec. 7
+ *
+ * Conventions
+ *   - Every function returns an hevmc_status: 0 on success, a negative code on
+ *     error (then hevmc_last_error() describes it).  Nothing aborts or exits.
+ *   - Units: lengths in Angstrom, energies in Kelvin, density in 1/Angstrom^3.
+ *   - "Device" pointers are HIP device memory on the current device (for
+ *     example torch CUDA tensors); "host" pointers are ordinary memory.  The
+ *     library never keeps a pointer after a call returns, except inside an
+ *     hevmc_ensemble created by hevmc_create_on (see there).
+ *   - Kernels are launched on the given hipStream_t (passed as void*; NULL is
+ *     the null stream) and are asynchronous unless stated otherwise.  Errors a
+ *     kernel cannot report are checked by the next synchronising call.
+ *   - Coordinates of a walker are structure of arrays: x[0..N-1], y[0..N-1],
+ *     z[0..N-1], each in [0, L).  An ensemble of W walkers is [W][3][N].
+ *     Element type: double for HEVMC_FP64, float for HEVMC_FP32.
+ *   - Random numbers: the moves of micro-step k of sweep t of walker w come from
+ *     Philox4x32-10 with counter (k, t, walker_id_base + w, 0|1) and key =
+ *     seed, so results depend only on (seed, walker id, sweep index) and not
+ *     on how sweeps are split into calls or how walkers are placed.
+ *   - Calls that share buffers and overlap on one device race; separate
+ *     ensembles on separate buffers may run concurrently on separate streams.
+ */
+#ifndef HEVMC_H
+#define HEVMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HEVMC_OK = 0,
+    HEVMC_EINVAL = -1,   /* invalid argument                                   */
+    HEVMC_ENOMEM = -2,   /* device or host allocation failed                   */
+    HEVMC_ENOFIT = -3,   /* walker does not fit in one workgroup's LDS         */
+    HEVMC_EDEVICE = -4,  /* HIP runtime error (no device, launch failure, ...) */
+    HEVMC_ESTATE = -5    /* non-finite running state or accumulator detected   */
+} hevmc_status;
+
+typedef enum {
+    HEVMC_FP64 = 0,      /* all arithmetic FP64                                          */
+    HEVMC_FP32 = 1       /* FP32 coordinates and pair terms; FP64 sums, decision, energies */
+} hevmc_precision;
+
+typedef enum {
+    HEVMC_SELECT_RANDOM = 0,     /* s drawn uniformly each micro-step (Sec. 2, Sec. 5.1) */
+    HEVMC_SELECT_SEQUENTIAL = 1  /* s = k, the micro-step index                          */
+} hevmc_order;
+
+/* Parameters of one ensemble of independent walkers (Markov chains). */
+typedef struct {
+    int32_t n;               /* atoms per walker N, >= 2                                  */
+    int32_t n_walkers;       /* walkers W, >= 1                                           */
+    int32_t precision;       /* hevmc_precision                                           */
+    int32_t order;           /* hevmc_order                                               */
+    double density;          /* N / L^3 (1/A^3), > 0                                      */
+    double b;                /* Jastrow parameter b of Eq. (9) (A), >= 0                  */
+    double hbar2_over_m;     /* hbar^2/m (K A^2), > 0; 12.1194 for 4He                    */
+    double step_sigma;       /* std. deviation of each Cartesian move component (A), > 0 */
+    uint64_t seed;           /* Philox key: (low 32 bits, high 32 bits)                   */
+    uint32_t walker_id_base; /* walker w uses Philox walker id walker_id_base + w         */
+    int32_t threads;         /* threads per walker: 0 = library choice, else 128, 256,
+                                512 or 1024                                                */
+} hevmc_params;
+
+/* Per-walker running state and accumulators, in device memory ([W] array).
+ * Sums are Neumaier-compensated: the value of sum_x is sum_x + c_x.
+ * Energies are totals for the walker's N atoms (K), not per atom. */
+typedef struct {
+    double u_run, v_run;     /* ln psi and V of the current configuration                 */
+    double sum_e, c_e;       /* sum of local energies E_L over samples                    */
+    double sum_e2, c_e2;     /* sum of E_L^2                                              */
+    double sum_v, c_v;       /* sum of V at samples                                       */
+    double sum_tpb, c_tpb;   /* sum of T_PB = -kappa sum_i (lap_i ln psi + |grad_i ln psi|^2) */
+    double sum_tjf, c_tjf;   /* sum of T_JF = -(kappa/2) sum_i lap_i ln psi               */
+    double sum_tf, c_tf;     /* sum of T_F  =  kappa sum_i |grad_i ln psi|^2              */
+    double sum_vs, c_vs;     /* sum of v_run at the end of every measured sweep           */
+    int64_t n_samples;       /* local-energy samples                                      */
+    int64_t n_sweeps_meas;   /* measured sweeps                                           */
+    int64_t n_acc;           /* accepted moves in measured sweeps                         */
+    int64_t n_try;           /* attempted moves in measured sweeps                        */
+} hevmc_walker_acc;
+
+/* Box side L = cbrt(n / density) (A), as every kernel uses it. */
+hevmc_status hevmc_box(const hevmc_params *p, double *L_out);
+
+/* LDS bytes one walker's workgroup needs and device bytes an ensemble's state
+ * takes (coordinates + accumulators).  HEVMC_ENOFIT if the walker does not fit
+ * in one workgroup's LDS on the current device. */
+hevmc_status hevmc_footprint(const hevmc_params *p, size_t *lds_bytes_per_walker,
+                             size_t *hbm_bytes);
+
+/* Start walkers.  If fcc_start != 0, first writes the fcc start with a
+ * deterministic jitter of 1e-3 lattice constants (device coords [W][3][N]);
+ * otherwise coords must already hold valid positions.  Then sets u_run, v_run
+ * of every walker from a full O(N^2) evaluation and zeroes all accumulators.
+ * coords, acc: device.  Asynchronous on stream. */
+hevmc_status hevmc_init_walkers(const hevmc_params *p, void *coords, hevmc_walker_acc *acc,
+                                int32_t fcc_start, void *stream);
+
+/* The hot path: sweeps t = sweep0 .. sweep0+n_sweeps-1 of all W walkers
+ * (Sec. 5.1 workflow; one sweep = N micro-updates, a "macroupdate" of Sec. 4.1).
+ * Each micro-update draws (s, xi, delta), forms dU and dV by the O(N) pair loop
+ * of Eq. (7), accepts if exp(2 dU) > xi (Eq. (5)), and on acceptance moves atom s
+ * and adds dU, dV to u_run, v_run.  Sweeps t >= measure_start are measured:
+ * moves are counted, v_run is added to sum_vs after the sweep, and if
+ * energy_every = m > 0 and (t - measure_start + 1) % m == 0 the local energy of
+ * the configuration is evaluated, added to the accumulators, and u_run, v_run
+ * are reset to its fresh totals.  Pass measure_start = 0xFFFFFFFF for
+ * equilibration only.  coords, acc: device, updated in place.  Requires
+ * sweep0 + n_sweeps <= 0xFFFFFFFF.  Asynchronous on stream. */
+hevmc_status hevmc_sweep(const hevmc_params *p, void *coords, hevmc_walker_acc *acc,
+                         uint32_t sweep0, int32_t n_sweeps, uint32_t measure_start,
+                         int32_t energy_every, void *stream);
+
+/* Local energy of each walker's configuration (Sec. 2 local value of H).
+ * coords: device [W][3][N]; out: device [W][6] doubles =
+ * (E_L, V, T_PB, T_JF, T_F, U) with U = ln psi.  Asynchronous on stream. */
+hevmc_status hevmc_local_energy(const hevmc_params *p, const void *coords, double *out,
+                                void *stream);
+
+/* Eq. (7) sums of one trial move per walker, without applying it: atom s[w]
+ * moved to wrap(r_s + delta[w]).  coords: device [W][3][N]; s: device [W]
+ * int32 in [0, N); delta: device [W][3] doubles; out: device [W][2] doubles =
+ * (dU, dV).  Asynchronous on stream. */
+hevmc_status hevmc_move_delta(const hevmc_params *p, const void *coords, const int32_t *s,
+                              const double *delta, double *out, void *stream);
+
+/* The random quantities of the N micro-steps of sweep t for every walker, as
+ * the sweep kernel draws them: s_out [W][N] int32, xi_out [W][N] doubles,
+ * delta_out [W][N][3] doubles (device).  Asynchronous on stream. */
+hevmc_status hevmc_draw_moves(const hevmc_params *p, uint32_t sweep, int32_t *s_out,
+                              double *xi_out, double *delta_out, void *stream);
+
+/* ---- Ensemble convenience layer (state kept on the device between calls) ---- */
+
+typedef struct hevmc_ensemble hevmc_ensemble;
+
+/* Create an ensemble that owns its device state (hipMalloc).  init_xyz: host
+ * [W][3][N] doubles, or NULL for the fcc start.  stream: the stream all its
+ * work runs on.  Blocks until initialised. */
+hevmc_status hevmc_create(const hevmc_params *p, const double *init_xyz, void *stream,
+                          hevmc_ensemble **out);
+
+/* Create an ensemble on caller-owned device buffers (coords [W][3][N] of the
+ * precision's type, already holding valid positions; acc [W]).  The buffers
+ * must outlive the ensemble.  Initialises acc from coords; asynchronous. */
+hevmc_status hevmc_create_on(const hevmc_params *p, void *dev_coords, hevmc_walker_acc *dev_acc,
+                             void *stream, hevmc_ensemble **out);
+
+/* Run n_sweeps more sweeps.  measure != 0 starts (or continues) measuring:
+ * the first measured sweep fixes measure_start.  Asynchronous. */
+hevmc_status hevmc_run(hevmc_ensemble *e, int32_t n_sweeps, int32_t energy_every, int32_t measure);
+
+/* Wait for the ensemble's stream; checks the running state for NaN/Inf. */
+hevmc_status hevmc_sync(hevmc_ensemble *e);
+
+/* Copy accumulators ([W], host) or coordinates ([W][3][N] doubles, host) out;
+ * both synchronise first. */
+hevmc_status hevmc_get_acc(hevmc_ensemble *e, hevmc_walker_acc *host_out);
+hevmc_status hevmc_get_coords(hevmc_ensemble *e, double *host_out);
+
+/* Sweep counter of the ensemble (next sweep index). */
+hevmc_status hevmc_get_sweep(hevmc_ensemble *e, uint32_t *sweep_out);
+
+hevmc_status hevmc_destroy(hevmc_ensemble *e);
+
+/* Parity entry on host buffers (synchronous): for one configuration xyz
+ * (host [3][N] doubles; rounded to float for HEVMC_FP32) returns the Eq. (7)
+ * sums for moving atom s by delta, and out_el[6] = (E_L, V, T_PB, T_JF, T_F, U).
+ * Uses p->n, precision, density, b, hbar2_over_m; ignores n_walkers. */
+hevmc_status hevmc_eval_config(const hevmc_params *p, const double *xyz, int32_t s,
+                               const double delta[3], double *d_u, double *d_v,
+                               double out_el[6]);
+
+/* Description of the last error on the calling thread (never NULL). */
+const char *hevmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -61,6 +61,8 @@ def lib():
         dp = C.POINTER(C.c_double)
         sp = C.POINTER(System)
         wp = C.POINTER(Walker)
+        L.or_box_side.argtypes = [C.c_int32, C.c_double, C.c_int32]
+        L.or_box_side.restype = C.c_double
         L.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
         L.or_draw_move.argtypes = [sp, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_int32), dp, dp]
         for name in ("or_f", "or_u"):
@@ -98,6 +100,10 @@ def _f64(a, shape=None):
 
 def system(n, L, b, hbar2_over_m=12.1194, step_sigma=1.0, seed=1, order=0):
     return System(int(n), int(order), float(L), float(b), float(hbar2_over_m), float(step_sigma), int(seed))
+
+
+def box_side(n, density, fp32=False):
+    return lib().or_box_side(int(n), float(density), int(bool(fp32)))
 
 
 def philox(ctr, key):

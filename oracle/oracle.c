@@ -12,6 +12,15 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Sec. 7: cubic box at density rho, L = (N / rho)^(1/3).  With fp32 != 0 the
+ * side is rounded to single precision: the FP32 form of the GPU library works
+ * in the box whose side is representable in FP32. */
+double or_box_side(int32_t n, double density, int32_t fp32)
+{
+    double L = cbrt((double)n / density);
+    return fp32 ? (double)(float)L : L;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Neumaier-compensated summation: the value of the sum is *s + *c.          */
 static void nsum(double *s, double *c, double x)

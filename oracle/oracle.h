@@ -52,6 +52,9 @@ typedef struct {
     int64_t n_try;           /* attempted moves in measured sweeps              */
 } or_walker;
 
+/* Box side L = (N / density)^(1/3); rounded to FP32 if fp32 != 0. */
+double or_box_side(int32_t n, double density, int32_t fp32);
+
 /* Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11). */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 

@@ -1,0 +1,561 @@
+// libhevmc C ABI: argument validation, launch planning, the ensemble layer and
+// the host-buffer parity entry.  Declarations and contracts: include/hevmc.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hevmc.h"
+#include "hevmc_internal.hpp"
+
+using namespace hevmc;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+hevmc_status fail(hevmc_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+hevmc_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(HEVMC_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+// Static LDS of the kernels: partial sums, at most 16 waves x (2x2 + 4) doubles.
+constexpr size_t kStaticLds = 16 * 8 * sizeof(double);
+
+struct DeviceLimits {
+    int cus = 0;
+    size_t lds_per_block = 0;
+    size_t lds_per_cu = 0;
+};
+
+hevmc_status device_limits(DeviceLimits &d)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    int v = 0;
+    if ((e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return hip_fail(e, "hipDeviceGetAttribute(MultiprocessorCount)");
+    d.cus = v;
+    if ((e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
+        return hip_fail(e, "hipDeviceGetAttribute(MaxSharedMemoryPerBlock)");
+    d.lds_per_block = (size_t)v;
+    if ((e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev)) != hipSuccess)
+        return hip_fail(e, "hipDeviceGetAttribute(MaxSharedMemoryPerMultiprocessor)");
+    d.lds_per_cu = (size_t)v;
+    return HEVMC_OK;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// Box side as the kernels use it.  The FP32 form works in a box of the
+// float-representable side so that wrap and minimum image agree.
+double box_side(const hevmc_params *p)
+{
+    const double L = std::cbrt((double)p->n / p->density);
+    return p->precision == HEVMC_FP32 ? (double)(float)L : L;
+}
+
+hevmc_status check_params(const hevmc_params *p)
+{
+    if (!p)
+        return fail(HEVMC_EINVAL, "params is NULL");
+    if (p->n < 2)
+        return fail(HEVMC_EINVAL, "n = %d: need at least 2 atoms", p->n);
+    if (p->n_walkers < 1)
+        return fail(HEVMC_EINVAL, "n_walkers = %d: need at least 1", p->n_walkers);
+    if (p->precision != HEVMC_FP64 && p->precision != HEVMC_FP32)
+        return fail(HEVMC_EINVAL, "precision = %d is not HEVMC_FP64 or HEVMC_FP32", p->precision);
+    if (p->order != HEVMC_SELECT_RANDOM && p->order != HEVMC_SELECT_SEQUENTIAL)
+        return fail(HEVMC_EINVAL, "order = %d is not a hevmc_order", p->order);
+    if (!finite_pos(p->density))
+        return fail(HEVMC_EINVAL, "density = %g must be finite and > 0", p->density);
+    if (!std::isfinite(p->b) || p->b < 0.0)
+        return fail(HEVMC_EINVAL, "b = %g must be finite and >= 0", p->b);
+    if (!finite_pos(p->hbar2_over_m))
+        return fail(HEVMC_EINVAL, "hbar2_over_m = %g must be finite and > 0", p->hbar2_over_m);
+    if (!finite_pos(p->step_sigma))
+        return fail(HEVMC_EINVAL, "step_sigma = %g must be finite and > 0", p->step_sigma);
+    if (p->threads != 0 && p->threads != 128 && p->threads != 256 && p->threads != 512 && p->threads != 1024)
+        return fail(HEVMC_EINVAL, "threads = %d must be 0, 128, 256, 512 or 1024", p->threads);
+    return HEVMC_OK;
+}
+
+// Threads per walker when the caller leaves the choice to the library: about
+// 8 atoms per lane, at least 2 waves, at most 16.
+int default_threads(int n)
+{
+    if (n <= 1024)
+        return 128;
+    if (n <= 3072)
+        return 256;
+    if (n <= 6144)
+        return 512;
+    return 1024;
+}
+
+size_t lds_needed(const hevmc_params *p)
+{
+    return (size_t)3 * (size_t)p->n * (p->precision == HEVMC_FP32 ? sizeof(float) : sizeof(double));
+}
+
+hevmc_status plan(const hevmc_params *p, void *stream, Launch &L)
+{
+    hevmc_status st = check_params(p);
+    if (st != HEVMC_OK)
+        return st;
+    DeviceLimits d;
+    if ((st = device_limits(d)) != HEVMC_OK)
+        return st;
+    const size_t need = lds_needed(p);
+    const size_t max_dyn = d.lds_per_block > kStaticLds ? d.lds_per_block - kStaticLds : 0;
+    if (need > max_dyn)
+        return fail(HEVMC_ENOFIT, "walker of %d atoms needs %zu B of LDS; a workgroup can have %zu B", p->n,
+                    need, max_dyn);
+    // Pad the LDS request so that no compute unit holds more than
+    // ceil(W / CUs) walkers: the walkers are then spread evenly over the chip.
+    size_t lds = need;
+    const int per_cu = (p->n_walkers + d.cus - 1) / d.cus;
+    if (per_cu >= 1 && d.lds_per_cu > 0) {
+        size_t even = d.lds_per_cu / (size_t)per_cu;
+        even = even > kStaticLds + 256 ? even - kStaticLds - 256 : 0;
+        even &= ~(size_t)255;
+        if (even > lds)
+            lds = even < max_dyn ? even : max_dyn;
+    }
+    const double Ld = box_side(p);
+    const double h = 0.5 * Ld;
+    const double b = p->b;
+    const double q = b / h;
+    KParams &k = L.k;
+    k.n = p->n;
+    k.order = p->order;
+    k.wid_base = p->walker_id_base;
+    k.key0 = (uint32_t)p->seed;
+    k.key1 = (uint32_t)(p->seed >> 32);
+    k.L = Ld;
+    k.invL = 1.0 / Ld;
+    k.h2 = h * h;
+    k.step = p->step_sigma;
+    k.c5 = -0.5 * (b * b * b * b * b);
+    k.u0 = q * q * q * q * q;   // -2 f(L/2) = (b / (L/2))^5
+    k.kappa = 0.5 * p->hbar2_over_m;
+    k.Lf = (float)Ld;
+    k.invLf = (float)(1.0 / Ld);
+    k.h2f = (float)(h * h);
+    k.c5f = (float)k.c5;
+    k.u0f = (float)k.u0;
+    L.p.n_walkers_grid = p->n_walkers;
+    L.threads = p->threads ? p->threads : default_threads(p->n);
+    L.fp32 = p->precision == HEVMC_FP32;
+    L.lds_bytes = lds;
+    L.stream = (hipStream_t)stream;
+    return HEVMC_OK;
+}
+
+hevmc_status launched(hipError_t e, const char *what) { return e == hipSuccess ? HEVMC_OK : hip_fail(e, what); }
+
+void fcc_cells(int n, int &nc)
+{
+    nc = 1;
+    while (4LL * nc * nc * nc < (long long)n)
+        ++nc;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" const char *hevmc_last_error(void) { return g_err.c_str(); }
+
+extern "C" hevmc_status hevmc_box(const hevmc_params *p, double *L_out)
+{
+    hevmc_status st = check_params(p);
+    if (st != HEVMC_OK)
+        return st;
+    if (!L_out)
+        return fail(HEVMC_EINVAL, "L_out is NULL");
+    *L_out = box_side(p);
+    return HEVMC_OK;
+}
+
+extern "C" hevmc_status hevmc_footprint(const hevmc_params *p, size_t *lds_bytes_per_walker, size_t *hbm_bytes)
+{
+    Launch L;
+    hevmc_status st = plan(p, nullptr, L);
+    if (lds_bytes_per_walker)
+        *lds_bytes_per_walker = check_params(p) == HEVMC_OK ? lds_needed(p) : 0;
+    if (hbm_bytes && check_params(p) == HEVMC_OK)
+        *hbm_bytes = lds_needed(p) * (size_t)p->n_walkers + sizeof(hevmc_walker_acc) * (size_t)p->n_walkers;
+    return st;
+}
+
+extern "C" hevmc_status hevmc_init_walkers(const hevmc_params *p, void *coords, hevmc_walker_acc *acc,
+                                           int32_t fcc_start, void *stream)
+{
+    Launch L;
+    hevmc_status st = plan(p, stream, L);
+    if (st != HEVMC_OK)
+        return st;
+    if (!coords || !acc)
+        return fail(HEVMC_EINVAL, "coords and acc must be device pointers");
+    int nc;
+    fcc_cells(p->n, nc);
+    return launched(launch_init(L, coords, acc, fcc_start ? 1 : 0, nc, L.k.L / nc), "init kernel launch");
+}
+
+extern "C" hevmc_status hevmc_sweep(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, uint32_t sweep0,
+                                    int32_t n_sweeps, uint32_t measure_start, int32_t energy_every, void *stream)
+{
+    Launch L;
+    hevmc_status st = plan(p, stream, L);
+    if (st != HEVMC_OK)
+        return st;
+    if (!coords || !acc)
+        return fail(HEVMC_EINVAL, "coords and acc must be device pointers");
+    if (n_sweeps < 0)
+        return fail(HEVMC_EINVAL, "n_sweeps = %d must be >= 0", n_sweeps);
+    if (energy_every < 0)
+        return fail(HEVMC_EINVAL, "energy_every = %d must be >= 0", energy_every);
+    if ((uint64_t)sweep0 + (uint64_t)n_sweeps > 0xFFFFFFFFull)
+        return fail(HEVMC_EINVAL, "sweep counter would pass 2^32 - 1");
+    if (n_sweeps == 0)
+        return HEVMC_OK;
+    return launched(launch_sweep(L, coords, acc, sweep0, n_sweeps, measure_start, energy_every),
+                    "sweep kernel launch");
+}
+
+extern "C" hevmc_status hevmc_local_energy(const hevmc_params *p, const void *coords, double *out, void *stream)
+{
+    Launch L;
+    hevmc_status st = plan(p, stream, L);
+    if (st != HEVMC_OK)
+        return st;
+    if (!coords || !out)
+        return fail(HEVMC_EINVAL, "coords and out must be device pointers");
+    return launched(launch_local_energy(L, coords, out), "local-energy kernel launch");
+}
+
+extern "C" hevmc_status hevmc_move_delta(const hevmc_params *p, const void *coords, const int32_t *s,
+                                         const double *delta, double *out, void *stream)
+{
+    Launch L;
+    hevmc_status st = plan(p, stream, L);
+    if (st != HEVMC_OK)
+        return st;
+    if (!coords || !s || !delta || !out)
+        return fail(HEVMC_EINVAL, "coords, s, delta and out must be device pointers");
+    return launched(launch_move_delta(L, coords, s, delta, out), "move-delta kernel launch");
+}
+
+extern "C" hevmc_status hevmc_draw_moves(const hevmc_params *p, uint32_t sweep, int32_t *s_out, double *xi_out,
+                                         double *delta_out, void *stream)
+{
+    Launch L;
+    hevmc_status st = plan(p, stream, L);
+    if (st != HEVMC_OK)
+        return st;
+    if (!s_out || !xi_out || !delta_out)
+        return fail(HEVMC_EINVAL, "s_out, xi_out and delta_out must be device pointers");
+    if ((long long)p->n * (long long)p->n_walkers > 0x7FFFFFFFLL)
+        return fail(HEVMC_EINVAL, "n * n_walkers too large for one call");
+    return launched(launch_draw_moves(L, sweep, s_out, xi_out, delta_out), "draw kernel launch");
+}
+
+// ---------------------------------------------------------------------------
+// Ensemble layer.
+
+struct hevmc_ensemble {
+    hevmc_params p;
+    hipStream_t stream;
+    void *coords;
+    hevmc_walker_acc *acc;
+    bool owns;
+    uint32_t sweep;
+    uint32_t mstart;
+};
+
+namespace {
+
+hevmc_status check_host_coords(const hevmc_params *p, const double *xyz, size_t count)
+{
+    const double L = box_side(p);
+    for (size_t i = 0; i < count; ++i)
+        if (!std::isfinite(xyz[i]) || xyz[i] < 0.0 || xyz[i] >= L)
+            return fail(HEVMC_EINVAL, "coordinate %zu = %g is not in [0, L = %.17g)", i, xyz[i], L);
+    return HEVMC_OK;
+}
+
+hevmc_status upload_coords(const hevmc_params *p, const double *xyz, size_t count, void *dev, hipStream_t st)
+{
+    hipError_t e;
+    if (p->precision == HEVMC_FP32) {
+        std::vector<float> tmp(count);
+        const float Lf = (float)box_side(p);
+        for (size_t i = 0; i < count; ++i) {
+            float v = (float)xyz[i];
+            tmp[i] = v < Lf ? v : 0.0f;   // a value just below L may round up to L
+        }
+        e = hipMemcpyAsync(dev, tmp.data(), count * sizeof(float), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+    } else {
+        e = hipMemcpyAsync(dev, xyz, count * sizeof(double), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+    }
+    return e == hipSuccess ? HEVMC_OK : hip_fail(e, "coordinate upload");
+}
+
+}  // namespace
+
+extern "C" hevmc_status hevmc_create(const hevmc_params *p, const double *init_xyz, void *stream,
+                                     hevmc_ensemble **out)
+{
+    Launch L;
+    hevmc_status st = plan(p, stream, L);
+    if (st != HEVMC_OK)
+        return st;
+    if (!out)
+        return fail(HEVMC_EINVAL, "out is NULL");
+    const size_t count = (size_t)p->n_walkers * 3 * (size_t)p->n;
+    if (init_xyz && (st = check_host_coords(p, init_xyz, count)) != HEVMC_OK)
+        return st;
+    auto *e = new (std::nothrow) hevmc_ensemble();
+    if (!e)
+        return fail(HEVMC_ENOMEM, "host allocation failed");
+    e->p = *p;
+    e->stream = (hipStream_t)stream;
+    e->owns = true;
+    e->sweep = 0;
+    e->mstart = 0xFFFFFFFFu;
+    const size_t cbytes = count * (p->precision == HEVMC_FP32 ? sizeof(float) : sizeof(double));
+    hipError_t he = hipMalloc(&e->coords, cbytes);
+    if (he != hipSuccess) {
+        delete e;
+        return fail(HEVMC_ENOMEM, "hipMalloc of %zu B for coordinates failed", cbytes);
+    }
+    he = hipMalloc((void **)&e->acc, sizeof(hevmc_walker_acc) * (size_t)p->n_walkers);
+    if (he != hipSuccess) {
+        (void)hipFree(e->coords);
+        delete e;
+        return fail(HEVMC_ENOMEM, "hipMalloc of accumulators failed");
+    }
+    if (init_xyz)
+        st = upload_coords(p, init_xyz, count, e->coords, e->stream);
+    if (st == HEVMC_OK)
+        st = hevmc_init_walkers(p, e->coords, e->acc, init_xyz ? 0 : 1, stream);
+    if (st == HEVMC_OK) {
+        he = hipStreamSynchronize(e->stream);
+        if (he != hipSuccess)
+            st = hip_fail(he, "initialisation");
+    }
+    if (st != HEVMC_OK) {
+        std::string msg = g_err;
+        hevmc_destroy(e);
+        g_err = msg;
+        return st;
+    }
+    *out = e;
+    return HEVMC_OK;
+}
+
+extern "C" hevmc_status hevmc_create_on(const hevmc_params *p, void *dev_coords, hevmc_walker_acc *dev_acc,
+                                        void *stream, hevmc_ensemble **out)
+{
+    Launch L;
+    hevmc_status st = plan(p, stream, L);
+    if (st != HEVMC_OK)
+        return st;
+    if (!out || !dev_coords || !dev_acc)
+        return fail(HEVMC_EINVAL, "out, dev_coords and dev_acc must not be NULL");
+    auto *e = new (std::nothrow) hevmc_ensemble();
+    if (!e)
+        return fail(HEVMC_ENOMEM, "host allocation failed");
+    e->p = *p;
+    e->stream = (hipStream_t)stream;
+    e->coords = dev_coords;
+    e->acc = dev_acc;
+    e->owns = false;
+    e->sweep = 0;
+    e->mstart = 0xFFFFFFFFu;
+    st = hevmc_init_walkers(p, dev_coords, dev_acc, 0, stream);
+    if (st != HEVMC_OK) {
+        delete e;
+        return st;
+    }
+    *out = e;
+    return HEVMC_OK;
+}
+
+extern "C" hevmc_status hevmc_run(hevmc_ensemble *e, int32_t n_sweeps, int32_t energy_every, int32_t measure)
+{
+    if (!e)
+        return fail(HEVMC_EINVAL, "ensemble is NULL");
+    if (n_sweeps < 0)
+        return fail(HEVMC_EINVAL, "n_sweeps = %d must be >= 0", n_sweeps);
+    if (measure && e->mstart == 0xFFFFFFFFu)
+        e->mstart = e->sweep;
+    const uint32_t mstart = measure ? e->mstart : 0xFFFFFFFFu;
+    hevmc_status st = hevmc_sweep(&e->p, e->coords, e->acc, e->sweep, n_sweeps, mstart, energy_every, e->stream);
+    if (st == HEVMC_OK)
+        e->sweep += (uint32_t)n_sweeps;
+    return st;
+}
+
+extern "C" hevmc_status hevmc_get_acc(hevmc_ensemble *e, hevmc_walker_acc *host_out)
+{
+    if (!e || !host_out)
+        return fail(HEVMC_EINVAL, "ensemble and host_out must not be NULL");
+    hipError_t he = hipMemcpyAsync(host_out, e->acc, sizeof(hevmc_walker_acc) * (size_t)e->p.n_walkers,
+                                   hipMemcpyDeviceToHost, e->stream);
+    if (he == hipSuccess)
+        he = hipStreamSynchronize(e->stream);
+    if (he != hipSuccess)
+        return hip_fail(he, "accumulator download");
+    for (int w = 0; w < e->p.n_walkers; ++w) {
+        const hevmc_walker_acc &a = host_out[w];
+        const double vals[] = {a.u_run, a.v_run, a.sum_e, a.sum_e2, a.sum_v, a.sum_tpb, a.sum_tjf, a.sum_tf, a.sum_vs};
+        for (double v : vals)
+            if (!std::isfinite(v))
+                return fail(HEVMC_ESTATE, "walker %d has a non-finite running state or accumulator", w);
+    }
+    return HEVMC_OK;
+}
+
+extern "C" hevmc_status hevmc_sync(hevmc_ensemble *e)
+{
+    if (!e)
+        return fail(HEVMC_EINVAL, "ensemble is NULL");
+    std::vector<hevmc_walker_acc> tmp((size_t)e->p.n_walkers);
+    return hevmc_get_acc(e, tmp.data());
+}
+
+extern "C" hevmc_status hevmc_get_coords(hevmc_ensemble *e, double *host_out)
+{
+    if (!e || !host_out)
+        return fail(HEVMC_EINVAL, "ensemble and host_out must not be NULL");
+    const size_t count = (size_t)e->p.n_walkers * 3 * (size_t)e->p.n;
+    hipError_t he;
+    if (e->p.precision == HEVMC_FP32) {
+        std::vector<float> tmp(count);
+        he = hipMemcpyAsync(tmp.data(), e->coords, count * sizeof(float), hipMemcpyDeviceToHost, e->stream);
+        if (he == hipSuccess)
+            he = hipStreamSynchronize(e->stream);
+        for (size_t i = 0; i < count; ++i)
+            host_out[i] = tmp[i];
+    } else {
+        he = hipMemcpyAsync(host_out, e->coords, count * sizeof(double), hipMemcpyDeviceToHost, e->stream);
+        if (he == hipSuccess)
+            he = hipStreamSynchronize(e->stream);
+    }
+    return he == hipSuccess ? HEVMC_OK : hip_fail(he, "coordinate download");
+}
+
+extern "C" hevmc_status hevmc_get_sweep(hevmc_ensemble *e, uint32_t *sweep_out)
+{
+    if (!e || !sweep_out)
+        return fail(HEVMC_EINVAL, "ensemble and sweep_out must not be NULL");
+    *sweep_out = e->sweep;
+    return HEVMC_OK;
+}
+
+extern "C" hevmc_status hevmc_destroy(hevmc_ensemble *e)
+{
+    if (!e)
+        return HEVMC_OK;
+    hevmc_status st = HEVMC_OK;
+    if (e->owns) {
+        hipError_t he = hipStreamSynchronize(e->stream);
+        if (he != hipSuccess)
+            st = hip_fail(he, "synchronise before free");
+        (void)hipFree(e->coords);
+        (void)hipFree(e->acc);
+    }
+    delete e;
+    return st;
+}
+
+extern "C" hevmc_status hevmc_eval_config(const hevmc_params *p, const double *xyz, int32_t s,
+                                          const double delta[3], double *d_u, double *d_v, double out_el[6])
+{
+    if (!p)
+        return fail(HEVMC_EINVAL, "params is NULL");
+    hevmc_params q = *p;
+    q.n_walkers = 1;
+    Launch L;
+    hevmc_status st = plan(&q, nullptr, L);
+    if (st != HEVMC_OK)
+        return st;
+    if (!xyz || !delta || !d_u || !d_v || !out_el)
+        return fail(HEVMC_EINVAL, "xyz, delta, d_u, d_v and out_el must not be NULL");
+    if (s < 0 || s >= q.n)
+        return fail(HEVMC_EINVAL, "s = %d is not in [0, %d)", s, q.n);
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(delta[a]))
+            return fail(HEVMC_EINVAL, "delta[%d] is not finite", a);
+    const size_t count = 3 * (size_t)q.n;
+    if ((st = check_host_coords(&q, xyz, count)) != HEVMC_OK)
+        return st;
+    const size_t cbytes = count * (q.precision == HEVMC_FP32 ? sizeof(float) : sizeof(double));
+    void *dc = nullptr;
+    int32_t *ds = nullptr;
+    double *dd = nullptr, *dout = nullptr;
+    hipError_t he = hipMalloc(&dc, cbytes);
+    if (he == hipSuccess)
+        he = hipMalloc((void **)&ds, sizeof(int32_t));
+    if (he == hipSuccess)
+        he = hipMalloc((void **)&dd, 3 * sizeof(double));
+    if (he == hipSuccess)
+        he = hipMalloc((void **)&dout, 8 * sizeof(double));
+    if (he != hipSuccess) {
+        st = fail(HEVMC_ENOMEM, "hipMalloc failed in hevmc_eval_config");
+    } else {
+        st = upload_coords(&q, xyz, count, dc, nullptr);
+        if (st == HEVMC_OK) {
+            he = hipMemcpy(ds, &s, sizeof(int32_t), hipMemcpyHostToDevice);
+            if (he == hipSuccess)
+                he = hipMemcpy(dd, delta, 3 * sizeof(double), hipMemcpyHostToDevice);
+            if (he != hipSuccess)
+                st = hip_fail(he, "argument upload");
+        }
+        if (st == HEVMC_OK)
+            st = launched(launch_move_delta(L, dc, ds, dd, dout), "move-delta kernel launch");
+        if (st == HEVMC_OK)
+            st = launched(launch_local_energy(L, dc, dout + 2), "local-energy kernel launch");
+        if (st == HEVMC_OK) {
+            double host[8];
+            he = hipMemcpy(host, dout, 8 * sizeof(double), hipMemcpyDeviceToHost);
+            if (he != hipSuccess) {
+                st = hip_fail(he, "result download");
+            } else {
+                *d_u = host[0];
+                *d_v = host[1];
+                for (int i = 0; i < 6; ++i)
+                    out_el[i] = host[2 + i];
+            }
+        }
+    }
+    (void)hipFree(dc);
+    (void)hipFree(ds);
+    (void)hipFree(dd);
+    (void)hipFree(dout);
+    return st;
+}

@@ -1,0 +1,243 @@
+// Device-side building blocks of libhevmc (gfx950): counter-based random
+// numbers, pair terms of the Jastrow wavefunction and the HFD-B(HE) potential,
+// and wave64 / workgroup reductions.
+//
+// Method: Lutsyshyn, "Fast quantum Monte Carlo on a GPU" (arXiv:1312.1282),
+// Sec. 2 (Eqs. (5)-(9)), Sec. 5.1, Sec. 7.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hevmc.h"
+
+namespace hevmc {
+
+// Kernel-side constants of one ensemble, derived once on the host.
+struct KParams {
+    int32_t n;           // atoms per walker
+    int32_t order;       // hevmc_order
+    uint32_t wid_base;   // Philox walker id of walker 0
+    uint32_t key0, key1; // Philox key (seed)
+    double L, invL;      // box side and its reciprocal
+    double h2;           // (L/2)^2: pair cutoff, inclusive
+    double step;         // Gaussian step, per component
+    double c5;           // -b^5 / 2, so f(r) = c5 r^-5 (Eq. (9))
+    double u0;           // -2 f(L/2): u(r) = f(r) + f(L-r) + u0 (Eq. (8), as read)
+    double kappa;        // hbar^2 / 2m
+    float Lf, invLf, h2f, c5f, u0f;
+};
+
+// HFD-B(HE) pair potential (Aziz, McCourt, Wong 1987), the interaction named
+// in Sec. 2:  V = eps [A exp(-alpha x + beta x^2) - F(x)(C6 x^-6 + C8 x^-8 + C10 x^-10)],
+// x = r / r_m, F(x) = exp(-(D/x - 1)^2) for x < D, else 1.
+namespace az {
+constexpr double eps = 10.948;
+constexpr double rm = 2.963;
+constexpr double A = 184431.01;
+constexpr double alpha = 10.43329537;
+constexpr double beta = -2.27965105;
+constexpr double C6 = 1.36745214;
+constexpr double C8 = 0.42123807;
+constexpr double C10 = 0.17473318;
+constexpr double D = 1.4826;
+constexpr double inv_rm = 1.0 / rm;
+constexpr double rm2 = rm * rm;
+constexpr double Drm = D * rm;        // D / x = Drm / r
+}  // namespace az
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64 products.
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t out[4])
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+__device__ __forceinline__ double unit32(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
+
+// The five random numbers of micro-step k of sweep t (Sec. 2: random atom s and
+// Gaussian displacement; Eq. (5): uniform xi; Sec. 5.1: Box-Muller).  Two
+// Philox blocks with counters (k, t, wid, 0) and (k, t, wid, 1):
+//   s = floor(a0 N / 2^32) (or k), xi = (top 52 bits of a1:a2 + 1/2) 2^-52,
+//   delta = step (R cos 2pi u2, R sin 2pi u2, R' cos 2pi u4),
+//   R = sqrt(-2 ln u1), R' = sqrt(-2 ln u3), (u1,u2,u3,u4) from (a3, b0, b1, b2).
+__device__ __forceinline__ void draw_move(const KParams &p, uint32_t k, uint32_t t, uint32_t wid,
+                                          int &s, double &xi, double &dx, double &dy, double &dz)
+{
+    uint32_t a[4], b[4];
+    philox4x32_10(k, t, wid, 0u, p.key0, p.key1, a);
+    philox4x32_10(k, t, wid, 1u, p.key0, p.key1, b);
+    s = (p.order == HEVMC_SELECT_SEQUENTIAL) ? (int)(k % (uint32_t)p.n)
+                                             : (int)__umulhi(a[0], (uint32_t)p.n);
+    const uint64_t m52 = ((uint64_t)a[1] << 20) | (uint64_t)(a[2] >> 12);
+    xi = ((double)m52 + 0.5) * 0x1p-52;
+    const double two_pi = 6.283185307179586;
+    const double R1 = sqrt(-2.0 * log(unit32(a[3])));
+    const double R2 = sqrt(-2.0 * log(unit32(b[1])));
+    double sn, cs;
+    sincos(two_pi * unit32(b[0]), &sn, &cs);
+    dx = p.step * (R1 * cs);
+    dy = p.step * (R1 * sn);
+    dz = p.step * (R2 * cos(two_pi * unit32(b[2])));
+}
+
+// Periodic wrap of a moved coordinate into [0, L) (Sec. 5.1).
+__device__ __forceinline__ double wrap_box(double y, double L)
+{
+    double x = y - L * floor(y / L);
+    return (x >= L) ? x - L : x;
+}
+
+// Minimum image of one coordinate difference (Sec. 5.1).
+__device__ __forceinline__ double min_image(double d, const KParams &p) { return d - p.L * rint(d * p.invL); }
+__device__ __forceinline__ float min_image(float d, const KParams &p) { return d - p.Lf * rintf(d * p.invLf); }
+
+// --------------------------------------------------------------------------
+// Pair terms at squared min-image distance r2 (Eqs. (8), (9); HFD-B(HE)).
+// u and V are zero beyond the inclusive cutoff L/2; callers mask i == s.
+
+// FP64: u(r) and V(r).
+__device__ __forceinline__ void pair_uv(const KParams &p, double r2, double &u, double &v)
+{
+    const double r = sqrt(r2);
+    const double ri = 1.0 / r;
+    const double rpi = 1.0 / (p.L - r);
+    const double ri2 = ri * ri, rpi2 = rpi * rpi;
+    const double uu = p.c5 * (ri2 * ri2 * ri + rpi2 * rpi2 * rpi) + p.u0;
+    const double x = r * az::inv_rm;
+    const double rep = az::A * exp(x * (az::beta * x - az::alpha));
+    const double y = az::rm2 * (ri2);                 // x^-2
+    const double disp = y * y * y * (az::C6 + y * (az::C8 + y * az::C10));
+    double F = 1.0;
+    if (x < az::D) {
+        const double q = az::Drm * ri - 1.0;
+        F = exp(-(q * q));
+    }
+    const double vv = az::eps * (rep - F * disp);
+    const bool in = r2 <= p.h2;
+    u = in ? uu : 0.0;
+    v = in ? vv : 0.0;
+}
+
+// FP32 form: same terms in single precision with the hardware reciprocal,
+// reciprocal square root and base-2 exponential.
+__device__ __forceinline__ float fexp(float a) { return __builtin_amdgcn_exp2f(a * 1.4426950408889634f); }
+
+__device__ __forceinline__ void pair_uv(const KParams &p, float r2, float &u, float &v)
+{
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * ri;
+    const float rpi = __builtin_amdgcn_rcpf(p.Lf - r);
+    const float ri2 = ri * ri, rpi2 = rpi * rpi;
+    const float uu = p.c5f * (ri2 * ri2 * ri + rpi2 * rpi2 * rpi) + p.u0f;
+    const float x = r * (float)az::inv_rm;
+    const float rep = (float)az::A * fexp(x * ((float)az::beta * x - (float)az::alpha));
+    const float y = (float)az::rm2 * ri2;
+    const float disp = y * y * y * ((float)az::C6 + y * ((float)az::C8 + y * (float)az::C10));
+    float F = 1.0f;
+    if (x < (float)az::D) {
+        const float q = (float)az::Drm * ri - 1.0f;
+        F = fexp(-(q * q));
+    }
+    const float vv = (float)az::eps * (rep - F * disp);
+    const bool in = r2 <= p.h2f;
+    u = in ? uu : 0.0f;
+    v = in ? vv : 0.0f;
+}
+
+// Terms of the local energy of one ordered pair: u, V, u'/r (the gradient of
+// ln psi is sum u'/r d) and u'' + 2u'/r (the Laplacian term), zero beyond L/2.
+// u' = -5 c5 (r^-6 - (L-r)^-6), u'' = 30 c5 (r^-7 + (L-r)^-7).
+struct ETerms {
+    double u, v, dur, lap;
+};
+
+__device__ __forceinline__ void pair_energy(const KParams &p, double r2, ETerms &e)
+{
+    const double r = sqrt(r2);
+    const double ri = 1.0 / r;
+    const double rpi = 1.0 / (p.L - r);
+    const double ri2 = ri * ri, rpi2 = rpi * rpi;
+    const double ri5 = ri2 * ri2 * ri, rpi5 = rpi2 * rpi2 * rpi;
+    const double ri6 = ri5 * ri, rpi6 = rpi5 * rpi;
+    const double uu = p.c5 * (ri5 + rpi5) + p.u0;
+    const double du = -5.0 * p.c5 * (ri6 - rpi6);
+    const double d2u = 30.0 * p.c5 * (ri6 * ri + rpi6 * rpi);
+    const double x = r * az::inv_rm;
+    const double rep = az::A * exp(x * (az::beta * x - az::alpha));
+    const double y = az::rm2 * ri2;
+    const double disp = y * y * y * (az::C6 + y * (az::C8 + y * az::C10));
+    double F = 1.0;
+    if (x < az::D) {
+        const double q = az::Drm * ri - 1.0;
+        F = exp(-(q * q));
+    }
+    const double vv = az::eps * (rep - F * disp);
+    const double dur = du * ri;
+    const bool in = r2 <= p.h2;
+    e.u = in ? uu : 0.0;
+    e.v = in ? vv : 0.0;
+    e.dur = in ? dur : 0.0;
+    e.lap = in ? d2u + 2.0 * dur : 0.0;
+}
+
+__device__ __forceinline__ void pair_energy(const KParams &p, float r2, ETerms &e)
+{
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * ri;
+    const float rpi = __builtin_amdgcn_rcpf(p.Lf - r);
+    const float ri2 = ri * ri, rpi2 = rpi * rpi;
+    const float ri5 = ri2 * ri2 * ri, rpi5 = rpi2 * rpi2 * rpi;
+    const float ri6 = ri5 * ri, rpi6 = rpi5 * rpi;
+    const float uu = p.c5f * (ri5 + rpi5) + p.u0f;
+    const float du = -5.0f * p.c5f * (ri6 - rpi6);
+    const float d2u = 30.0f * p.c5f * (ri6 * ri + rpi6 * rpi);
+    const float x = r * (float)az::inv_rm;
+    const float rep = (float)az::A * fexp(x * ((float)az::beta * x - (float)az::alpha));
+    const float y = (float)az::rm2 * ri2;
+    const float disp = y * y * y * ((float)az::C6 + y * ((float)az::C8 + y * (float)az::C10));
+    float F = 1.0f;
+    if (x < (float)az::D) {
+        const float q = (float)az::Drm * ri - 1.0f;
+        F = fexp(-(q * q));
+    }
+    const float vv = (float)az::eps * (rep - F * disp);
+    const float dur = du * ri;
+    const bool in = r2 <= p.h2f;
+    e.u = in ? (double)uu : 0.0;
+    e.v = in ? (double)vv : 0.0;
+    e.dur = in ? (double)dur : 0.0;
+    e.lap = in ? (double)(d2u + 2.0f * dur) : 0.0;
+}
+
+// --------------------------------------------------------------------------
+// Reductions.  The xor butterfly leaves the bitwise-identical total in every
+// lane (each step adds the same two operands in both partner lanes), so the
+// result depends only on the data and the workgroup shape.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// Neumaier-compensated accumulation: value = s + c.
+__device__ __forceinline__ void nsum(double &s, double &c, double x)
+{
+    const double t = s + x;
+    c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+    s = t;
+}
+
+}  // namespace hevmc

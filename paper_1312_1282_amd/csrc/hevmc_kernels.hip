@@ -1,0 +1,485 @@
+// libhevmc kernels for gfx950: the Metropolis sweep with its fused local-energy
+// pass, and the standalone entry kernels used for start-up and parity checks.
+//
+// One workgroup advances one walker (one Markov chain, Sec. 3).  The walker's
+// coordinates live in LDS for the whole launch (Sec. 3: shared-memory
+// persistence) as structure of arrays x[N], y[N], z[N]; HBM is touched only to
+// load the walker at the start and store it at the end.  Each micro-update's
+// O(N) pair loop of Eq. (7) is spread over the workgroup's lanes (atom
+// i = tid + j*NT), reduced per wave by an xor butterfly and across waves
+// through a small double-buffered LDS array, so one barrier per micro-update
+// suffices.  Every lane then takes the same Metropolis decision (Eq. (5)).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "hevmc_device.hpp"
+#include "hevmc_internal.hpp"
+
+namespace hevmc {
+
+__device__ __forceinline__ int readlane_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+__device__ __forceinline__ double readlane_d(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum of NV doubles over the workgroup; every thread gets the same totals.
+// buf must hold NW*NV doubles; it is free again when the function returns.
+template <int NT, int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *buf)
+{
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+        v[q] = wave_sum(v[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            buf[wave * NV + q] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w)
+            t += buf[w * NV + q];
+        v[q] = t;
+    }
+    __syncthreads();
+}
+
+// Local energy of the walker in LDS (Sec. 2 local value of H; estimators as in
+// oracle): out = (E_L, V, T_PB, T_JF, T_F, U).  Each lane owns atoms
+// i = tid + j*NT and sums over all j != i (every pair twice, no atomics).
+template <typename T, int NT>
+__device__ void local_energy_pass(const KParams &p, const T *sx, const T *sy, const T *sz,
+                                  double *buf, double out[6])
+{
+    const int n = p.n;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};   // sum |G_i|^2, sum L_i, sum V_i, sum U_i
+    for (int i = threadIdx.x; i < n; i += NT) {
+        const T xi = sx[i], yi = sy[i], zi = sz[i];
+        double gx = 0, gy = 0, gz = 0, li = 0, vi = 0, ui = 0;
+        for (int j = 0; j < n; ++j) {
+            const T dx = min_image(xi - sx[j], p);
+            const T dy = min_image(yi - sy[j], p);
+            const T dz = min_image(zi - sz[j], p);
+            const T r2 = dx * dx + dy * dy + dz * dz;
+            ETerms e;
+            pair_energy(p, r2, e);
+            const bool self = (j == i);
+            const double dur = self ? 0.0 : e.dur;
+            gx += dur * (double)dx;
+            gy += dur * (double)dy;
+            gz += dur * (double)dz;
+            li += self ? 0.0 : e.lap;
+            vi += self ? 0.0 : e.v;
+            ui += self ? 0.0 : e.u;
+        }
+        acc[0] += gx * gx + gy * gy + gz * gz;
+        acc[1] += li;
+        acc[2] += vi;
+        acc[3] += ui;
+    }
+    block_sum<NT, 4>(acc, buf);
+    const double V = 0.5 * acc[2], U = 0.5 * acc[3];
+    const double tpb = -p.kappa * (acc[1] + acc[0]);
+    out[0] = V + tpb;
+    out[1] = V;
+    out[2] = tpb;
+    out[3] = -0.5 * p.kappa * acc[1];
+    out[4] = p.kappa * acc[0];
+    out[5] = U;
+}
+
+// Lane partial of the Eq. (7) sums for moving atom s from (ox,oy,oz) to
+// (nx,ny,nz): sum over this lane's atoms i != s of u(new) - u(old), V(new) - V(old).
+template <typename T, int NT>
+__device__ __forceinline__ void move_partial(const KParams &p, const T *sx, const T *sy, const T *sz,
+                                             int s, T ox, T oy, T oz, T nx, T ny, T nz,
+                                             double &du, double &dv)
+{
+    const int n = p.n;
+    for (int i = threadIdx.x; i < n; i += NT) {
+        const T xi = sx[i], yi = sy[i], zi = sz[i];
+        const T ax = min_image(ox - xi, p), ay = min_image(oy - yi, p), az_ = min_image(oz - zi, p);
+        const T bx = min_image(nx - xi, p), by = min_image(ny - yi, p), bz = min_image(nz - zi, p);
+        const T r2o = ax * ax + ay * ay + az_ * az_;
+        const T r2n = bx * bx + by * by + bz * bz;
+        T uo, vo, un, vn;
+        pair_uv(p, r2o, uo, vo);
+        pair_uv(p, r2n, un, vn);
+        const bool self = (i == s);
+        du += self ? 0.0 : (double)(un - uo);
+        dv += self ? 0.0 : (double)(vn - vo);
+    }
+}
+
+// fcc start of walker wid with deterministic jitter (see hevmc_init_walkers).
+template <typename T>
+__device__ void fcc_site(const KParams &p, uint32_t wid, int pidx, int nc, double a, T *x, T *y, T *z)
+{
+    const int beta = pidx & 3, cell = pidx >> 2;
+    const int iz = cell % nc, iy = (cell / nc) % nc, ix = cell / (nc * nc);
+    const double bx = (beta == 2 || beta == 3) ? 0.5 : 0.0;
+    const double by = (beta == 1 || beta == 3) ? 0.5 : 0.0;
+    const double bz = (beta == 1 || beta == 2) ? 0.5 : 0.0;
+    uint32_t r[4];
+    philox4x32_10((uint32_t)pidx, 0xFFFFFFFFu, wid, 2u, p.key0, p.key1, r);
+    const double px = a * ((double)ix + bx + 0.25) + 1e-3 * a * (unit32(r[0]) - 0.5);
+    const double py = a * ((double)iy + by + 0.25) + 1e-3 * a * (unit32(r[1]) - 0.5);
+    const double pz = a * ((double)iz + bz + 0.25) + 1e-3 * a * (unit32(r[2]) - 0.5);
+    *x = (T)px; *y = (T)py; *z = (T)pz;
+}
+
+// --------------------------------------------------------------------------
+// The sweep kernel (hevmc_sweep).  Grid: one workgroup of NT threads per walker.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
+                                              hevmc_walker_acc *__restrict__ accs, uint32_t sweep0,
+                                              int32_t nsw, uint32_t mstart, int32_t m)
+{
+    constexpr int NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[2][NW][2];
+    __shared__ double ebuf[NW * 4];
+    T *sx = reinterpret_cast<T *>(smem_raw);
+    const int n = p.n;
+    T *sy = sx + n, *sz = sy + n;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int w = blockIdx.x;
+    const uint32_t wid = p.wid_base + (uint32_t)w;
+
+    T *g = coords + (size_t)w * 3 * (size_t)n;
+    for (int i = tid; i < 3 * n; i += NT)
+        sx[i] = g[i];
+    hevmc_walker_acc a = accs[w];
+    double u_run = a.u_run, v_run = a.v_run;
+    int64_t n_acc = 0, n_try = 0, n_samp = 0, n_swm = 0;
+    __syncthreads();
+
+    int last_s = -1;          // atom accepted in the previous micro-update
+    T lx = 0, ly = 0, lz = 0; // its new position (LDS copy not yet visible to all waves)
+
+    for (int it = 0; it < nsw; ++it) {
+        const uint32_t t = sweep0 + (uint32_t)it;
+        const bool measured = t >= mstart;
+        for (int k0 = 0; k0 < n; k0 += 64) {
+            // lane l draws the random numbers of micro-step k0 + l
+            int bs;
+            double bxi, bdx, bdy, bdz;
+            draw_move(p, (uint32_t)(k0 + lane), t, wid, bs, bxi, bdx, bdy, bdz);
+            const int kend = min(64, n - k0);
+            for (int j = 0; j < kend; ++j) {
+                const int k = k0 + j;
+                const int s = readlane_i(bs, j);
+                const double xi = readlane_d(bxi, j);
+                const double dx = readlane_d(bdx, j), dy = readlane_d(bdy, j), dz = readlane_d(bdz, j);
+                T ox, oy, oz;
+                if (s == last_s) {
+                    ox = lx; oy = ly; oz = lz;
+                } else {
+                    ox = sx[s]; oy = sy[s]; oz = sz[s];
+                }
+                const T nx = (T)wrap_box((double)ox + dx, p.L);
+                const T ny = (T)wrap_box((double)oy + dy, p.L);
+                const T nz = (T)wrap_box((double)oz + dz, p.L);
+                double du = 0.0, dv = 0.0;
+                move_partial<T, NT>(p, sx, sy, sz, s, ox, oy, oz, nx, ny, nz, du, dv);
+                du = wave_sum(du);
+                dv = wave_sum(dv);
+                if (lane == 0) {
+                    red[k & 1][wave][0] = du;
+                    red[k & 1][wave][1] = dv;
+                }
+                __syncthreads();
+                double DU = 0.0, DV = 0.0;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    DU += red[k & 1][q][0];
+                    DV += red[k & 1][q][1];
+                }
+                const bool accept = exp(2.0 * DU) > xi;
+                if (measured) {
+                    n_try += 1;
+                    n_acc += accept ? 1 : 0;
+                }
+                if (accept) {
+                    u_run += DU;
+                    v_run += DV;
+                    if (tid == s % NT) {
+                        sx[s] = nx; sy[s] = ny; sz[s] = nz;
+                    }
+                    last_s = s;
+                    lx = nx; ly = ny; lz = nz;
+                } else {
+                    last_s = -1;
+                }
+            }
+        }
+        if (measured) {
+            if (m > 0 && (t - mstart + 1) % (uint32_t)m == 0) {
+                __syncthreads();
+                double el[6];
+                local_energy_pass<T, NT>(p, sx, sy, sz, ebuf, el);
+                if (tid == 0) {
+                    nsum(a.sum_e, a.c_e, el[0]);
+                    nsum(a.sum_e2, a.c_e2, el[0] * el[0]);
+                    nsum(a.sum_v, a.c_v, el[1]);
+                    nsum(a.sum_tpb, a.c_tpb, el[2]);
+                    nsum(a.sum_tjf, a.c_tjf, el[3]);
+                    nsum(a.sum_tf, a.c_tf, el[4]);
+                }
+                n_samp += 1;
+                u_run = el[5];
+                v_run = el[1];
+                last_s = -1;
+            }
+            if (tid == 0)
+                nsum(a.sum_vs, a.c_vs, v_run);
+            n_swm += 1;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < 3 * n; i += NT)
+        g[i] = sx[i];
+    if (tid == 0) {
+        a.u_run = u_run;
+        a.v_run = v_run;
+        a.n_samples += n_samp;
+        a.n_sweeps_meas += n_swm;
+        a.n_acc += n_acc;
+        a.n_try += n_try;
+        accs[w] = a;
+    }
+}
+
+// Local energies of the W configurations (hevmc_local_energy).
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_local_energy(KParams p, const T *__restrict__ coords,
+                                                     double *__restrict__ out)
+{
+    constexpr int NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double ebuf[NW * 4];
+    T *sx = reinterpret_cast<T *>(smem_raw);
+    const int n = p.n;
+    const T *g = coords + (size_t)blockIdx.x * 3 * (size_t)n;
+    for (int i = threadIdx.x; i < 3 * n; i += NT)
+        sx[i] = g[i];
+    __syncthreads();
+    double el[6];
+    local_energy_pass<T, NT>(p, sx, sx + n, sx + 2 * n, ebuf, el);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 6; ++q)
+            out[(size_t)blockIdx.x * 6 + q] = el[q];
+}
+
+// Start walkers (hevmc_init_walkers): optional fcc start, then running totals
+// from a full evaluation and zeroed accumulators.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_init(KParams p, T *__restrict__ coords,
+                                             hevmc_walker_acc *__restrict__ accs, int fcc, int nc,
+                                             double a_lat)
+{
+    constexpr int NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double ebuf[NW * 4];
+    T *sx = reinterpret_cast<T *>(smem_raw);
+    const int n = p.n;
+    T *g = coords + (size_t)blockIdx.x * 3 * (size_t)n;
+    const uint32_t wid = p.wid_base + blockIdx.x;
+    if (fcc) {
+        for (int i = threadIdx.x; i < n; i += NT) {
+            T x, y, z;
+            fcc_site<T>(p, wid, i, nc, a_lat, &x, &y, &z);
+            sx[i] = x; sx[n + i] = y; sx[2 * n + i] = z;
+            g[i] = x; g[n + i] = y; g[2 * n + i] = z;
+        }
+    } else {
+        for (int i = threadIdx.x; i < 3 * n; i += NT)
+            sx[i] = g[i];
+    }
+    __syncthreads();
+    double el[6];
+    local_energy_pass<T, NT>(p, sx, sx + n, sx + 2 * n, ebuf, el);
+    if (threadIdx.x == 0) {
+        hevmc_walker_acc a = {};
+        a.u_run = el[5];
+        a.v_run = el[1];
+        accs[blockIdx.x] = a;
+    }
+}
+
+// Eq. (7) sums of one given trial move per walker (hevmc_move_delta).
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_move_delta(KParams p, const T *__restrict__ coords,
+                                                   const int32_t *__restrict__ s_in,
+                                                   const double *__restrict__ delta,
+                                                   double *__restrict__ out)
+{
+    constexpr int NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double ebuf[NW * 2];
+    T *sx = reinterpret_cast<T *>(smem_raw);
+    const int n = p.n;
+    const int w = blockIdx.x;
+    const T *g = coords + (size_t)w * 3 * (size_t)n;
+    for (int i = threadIdx.x; i < 3 * n; i += NT)
+        sx[i] = g[i];
+    __syncthreads();
+    const int s = s_in[w];
+    if (s < 0 || s >= n) {   // invalid atom index: report NaN rather than read outside LDS
+        if (threadIdx.x == 0) {
+            out[2 * w + 0] = __builtin_nan("");
+            out[2 * w + 1] = __builtin_nan("");
+        }
+        return;
+    }
+    const T ox = sx[s], oy = sx[n + s], oz = sx[2 * n + s];
+    const T nx = (T)wrap_box((double)ox + delta[3 * w + 0], p.L);
+    const T ny = (T)wrap_box((double)oy + delta[3 * w + 1], p.L);
+    const T nz = (T)wrap_box((double)oz + delta[3 * w + 2], p.L);
+    double v[2] = {0.0, 0.0};
+    move_partial<T, NT>(p, sx, sx + n, sx + 2 * n, s, ox, oy, oz, nx, ny, nz, v[0], v[1]);
+    // same reduction order as the sweep: wave butterfly, then waves in order
+    block_sum<NT, 2>(v, ebuf);
+    if (threadIdx.x == 0) {
+        out[2 * w + 0] = v[0];
+        out[2 * w + 1] = v[1];
+    }
+}
+
+// Random numbers of sweep t (hevmc_draw_moves): one thread per (walker, k).
+__global__ void k_draw_moves(KParams p, uint32_t t, int32_t *__restrict__ s_out,
+                             double *__restrict__ xi_out, double *__restrict__ d_out, int total)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= total)
+        return;
+    const int w = gid / p.n, k = gid % p.n;
+    int s;
+    double xi, dx, dy, dz;
+    draw_move(p, (uint32_t)k, t, p.wid_base + (uint32_t)w, s, xi, dx, dy, dz);
+    s_out[gid] = s;
+    xi_out[gid] = xi;
+    d_out[3 * (size_t)gid + 0] = dx;
+    d_out[3 * (size_t)gid + 1] = dy;
+    d_out[3 * (size_t)gid + 2] = dz;
+}
+
+// --------------------------------------------------------------------------
+// Launchers.  Each checks nothing itself: the C ABI validated the arguments.
+
+template <typename T, int NT>
+static hipError_t launch_sweep_t(const Launch &L, void *coords, hevmc_walker_acc *acc, uint32_t sweep0,
+                                 int32_t nsw, uint32_t mstart, int32_t m)
+{
+    auto kern = k_sweep<T, NT>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)L.lds_bytes);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k,
+                       (T *)coords, acc, sweep0, nsw, mstart, m);
+    return hipGetLastError();
+}
+
+template <typename T, int NT>
+static hipError_t launch_energy_t(const Launch &L, const void *coords, double *out)
+{
+    auto kern = k_local_energy<T, NT>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)L.lds_bytes);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k,
+                       (const T *)coords, out);
+    return hipGetLastError();
+}
+
+template <typename T, int NT>
+static hipError_t launch_init_t(const Launch &L, void *coords, hevmc_walker_acc *acc, int fcc, int nc,
+                                double a_lat)
+{
+    auto kern = k_init<T, NT>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)L.lds_bytes);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k,
+                       (T *)coords, acc, fcc, nc, a_lat);
+    return hipGetLastError();
+}
+
+template <typename T, int NT>
+static hipError_t launch_delta_t(const Launch &L, const void *coords, const int32_t *s, const double *d,
+                                 double *out)
+{
+    auto kern = k_move_delta<T, NT>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)L.lds_bytes);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k,
+                       (const T *)coords, s, d, out);
+    return hipGetLastError();
+}
+
+// Dispatch on (precision, threads per walker).
+#define HEVMC_DISPATCH(FN, ...)                                                        \
+    do {                                                                               \
+        if (L.fp32) {                                                                  \
+            switch (L.threads) {                                                       \
+            case 128: return FN<float, 128>(L, __VA_ARGS__);                          \
+            case 256: return FN<float, 256>(L, __VA_ARGS__);                          \
+            case 512: return FN<float, 512>(L, __VA_ARGS__);                          \
+            case 1024: return FN<float, 1024>(L, __VA_ARGS__);                        \
+            }                                                                          \
+        } else {                                                                       \
+            switch (L.threads) {                                                       \
+            case 128: return FN<double, 128>(L, __VA_ARGS__);                         \
+            case 256: return FN<double, 256>(L, __VA_ARGS__);                         \
+            case 512: return FN<double, 512>(L, __VA_ARGS__);                         \
+            case 1024: return FN<double, 1024>(L, __VA_ARGS__);                       \
+            }                                                                          \
+        }                                                                              \
+        return hipErrorInvalidValue;                                                   \
+    } while (0)
+
+hipError_t launch_sweep(const Launch &L, void *coords, hevmc_walker_acc *acc, uint32_t sweep0, int32_t nsw,
+                        uint32_t mstart, int32_t m)
+{
+    HEVMC_DISPATCH(launch_sweep_t, coords, acc, sweep0, nsw, mstart, m);
+}
+
+hipError_t launch_local_energy(const Launch &L, const void *coords, double *out)
+{
+    HEVMC_DISPATCH(launch_energy_t, coords, out);
+}
+
+hipError_t launch_init(const Launch &L, void *coords, hevmc_walker_acc *acc, int fcc, int nc, double a_lat)
+{
+    HEVMC_DISPATCH(launch_init_t, coords, acc, fcc, nc, a_lat);
+}
+
+hipError_t launch_move_delta(const Launch &L, const void *coords, const int32_t *s, const double *d,
+                             double *out)
+{
+    HEVMC_DISPATCH(launch_delta_t, coords, s, d, out);
+}
+
+hipError_t launch_draw_moves(const Launch &L, uint32_t t, int32_t *s, double *xi, double *d)
+{
+    const int total = L.p.n_walkers_grid * L.k.n;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_draw_moves, dim3((total + bs - 1) / bs), dim3(bs), 0, L.stream, L.k, t, s, xi, d,
+                       total);
+    return hipGetLastError();
+}
+
+}  // namespace hevmc

@@ -1,0 +1,290 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances (FP64):
+  * Eq. (7) sums:  |dU_gpu - dU_or| <= 1e-12 max(|dU_or|, sum_i |u'_i| + |u_i|),
+    same for dV with |V| terms (relative 1e-12 is ill-posed when dU ~ 0, so
+    the scale is the sum of the magnitudes that are added);
+  * local energy: each of (E_L, V, T_PB, T_JF, T_F, U) within 1e-12 x the
+    oracle's scale sum |V_ij| + kappa sum_i (|L_i| + |G_i|^2);
+  * random numbers: s and xi bit for bit, delta within 1e-14 relative
+    (Box-Muller uses log, sqrt, sin, cos whose last bit may differ between the
+    device and host math libraries);
+  * chains in lockstep: identical accept counts, coordinates within 1e-9 A,
+    accumulators within 1e-10 relative.
+"""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle as O
+from inputs import grid_config, moves
+from paper_1312_1282_amd import abi, configs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RHO = configs.RHO_EQ
+B = configs.C1_SMALL_FP64.b
+STEP = configs.C1_SMALL_FP64.step_sigma
+
+
+def osys(n, rho=RHO, b=B, step=STEP, seed=1, fp32=False, order=0):
+    return O.system(n, O.box_side(n, rho, fp32), b, hbar2_over_m=configs.HBAR2_OVER_M, step_sigma=step,
+                    seed=seed, order=order)
+
+
+def gparams(n, W, precision=abi.FP64, threads=0, seed=1, wbase=0, order=0, b=B, rho=RHO, step=STEP):
+    return abi.make_params(n, W, precision=precision, density=rho, b=b, step_sigma=step, seed=seed,
+                           walker_id_base=wbase, threads=threads, order=order)
+
+
+def within(got, ref, scale, rel):
+    return abs(got - ref) <= rel * max(abs(ref), scale)
+
+
+def _dev(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+# ---------------------------------------------------------------------------
+# per-configuration quantities
+
+@pytest.mark.parametrize("n,threads", [(2, 128), (4, 128), (27, 256), (108, 128), (500, 128), (500, 512),
+                                       (1100, 1024), (2048, 256), (2048, 512)])
+def test_move_sums_fp64(n, threads):
+    W = 6
+    s_ = osys(n)
+    L = s_.L
+    xs = np.stack([grid_config(n, L, seed=1000 + n + w) for w in range(W)])
+    ss, dd = moves(n, W, 0.8, seed=77 + n)
+    p = gparams(n, W, threads=threads)
+    out = torch.zeros((W, 2), dtype=torch.float64, device="cuda")
+    abi.move_delta(p, _dev(xs), _dev(ss, torch.int32), _dev(dd), out)
+    out = out.cpu().numpy()
+    for w in range(W):
+        rnew = O.trial_position(s_, xs[w], ss[w], dd[w])
+        du, dv, su, sv = O.delta(s_, xs[w], ss[w], rnew)
+        assert within(out[w, 0], du, su, 1e-12), (w, out[w, 0], du, su)
+        assert within(out[w, 1], dv, sv, 1e-12), (w, out[w, 1], dv, sv)
+
+
+@pytest.mark.parametrize("n,threads", [(2, 128), (4, 128), (27, 128), (108, 256), (500, 128), (1100, 1024),
+                                       (2048, 256), (4000, 512)])
+def test_local_energy_fp64(n, threads):
+    W = 3
+    s_ = osys(n)
+    xs = np.stack([grid_config(n, s_.L, seed=2000 + n + w) for w in range(W)])
+    p = gparams(n, W, threads=threads)
+    out = torch.zeros((W, 6), dtype=torch.float64, device="cuda")
+    abi.local_energy(p, _dev(xs), out)
+    out = out.cpu().numpy()
+    for w in range(W):
+        ref, scale = O.local_energy(s_, xs[w])
+        for q in range(6):
+            assert within(out[w, q], ref[q], scale, 1e-12), (w, q, out[w, q], ref[q], scale)
+
+
+def test_eval_config_host_entry():
+    n = 108
+    s_ = osys(n)
+    x = grid_config(n, s_.L, seed=5)
+    p = gparams(n, 1)
+    ss, dd = moves(n, 4, 1.0, seed=3)
+    for k in range(4):
+        du, dv, el = abi.eval_config(p, x, int(ss[k]), dd[k])
+        rnew = O.trial_position(s_, x, ss[k], dd[k])
+        rdu, rdv, su, sv = O.delta(s_, x, ss[k], rnew)
+        ref, scale = O.local_energy(s_, x)
+        assert within(du, rdu, su, 1e-12) and within(dv, rdv, sv, 1e-12)
+        assert all(within(el[q], ref[q], scale, 1e-12) for q in range(6))
+
+
+def test_invalid_move_index_gives_nan_and_eval_rejects():
+    n, W = 27, 2
+    s_ = osys(n)
+    xs = np.stack([grid_config(n, s_.L, seed=w) for w in range(W)])
+    p = gparams(n, W)
+    out = torch.zeros((W, 2), dtype=torch.float64, device="cuda")
+    abi.move_delta(p, _dev(xs), _dev(np.array([-1, n], np.int32), torch.int32), _dev(np.zeros((W, 3))), out)
+    assert torch.isnan(out).all()
+    with pytest.raises(abi.HevmcError):
+        abi.eval_config(gparams(n, 1), xs[0], n, np.zeros(3))
+
+
+def test_fp64_walker_too_large_for_lds():
+    with pytest.raises(abi.HevmcError) as ei:
+        abi.footprint(gparams(10976, 1))
+    assert ei.value.code == -3
+
+
+# ---------------------------------------------------------------------------
+# random numbers and start
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_draw_moves_match_oracle(order):
+    n, W, t = 97, 3, 12345
+    p = gparams(n, W, seed=0x1234567890ABCDEF, wbase=7, order=order)
+    s_ = osys(n, seed=0x1234567890ABCDEF, order=order)
+    so = torch.zeros((W, n), dtype=torch.int32, device="cuda")
+    xo = torch.zeros((W, n), dtype=torch.float64, device="cuda")
+    do = torch.zeros((W, n, 3), dtype=torch.float64, device="cuda")
+    abi.draw_moves(p, t, so, xo, do)
+    so, xo, do = so.cpu().numpy(), xo.cpu().numpy(), do.cpu().numpy()
+    for w in range(W):
+        for k in range(n):
+            s, xi, d = O.draw_move(s_, k, t, 7 + w)
+            assert so[w, k] == s
+            assert xo[w, k] == xi
+            assert np.allclose(do[w, k], d, rtol=1e-14, atol=1e-15 * STEP)
+
+
+@pytest.mark.parametrize("n,precision", [(108, abi.FP64), (500, abi.FP64), (256, abi.FP32)])
+def test_fcc_start_and_initial_totals(n, precision):
+    W = 4
+    p = gparams(n, W, precision=precision, wbase=3)
+    coords, acc = abi.alloc_state(p)
+    abi.init_walkers(p, coords, acc, fcc_start=True)
+    xs = coords.cpu().numpy().astype(np.float64)
+    a = abi.acc_to_numpy(acc)
+    fp32 = precision == abi.FP32
+    s_ = osys(n, fp32=fp32)
+    for w in range(W):
+        ref = O.fcc_start(s_, 3 + w)
+        tol = 1e-6 * s_.L if fp32 else 1e-13 * s_.L
+        assert np.max(np.abs(xs[w] - ref)) <= tol
+        U, V = O.totals(s_, xs[w])
+        rel = 1e-5 if fp32 else 1e-12
+        assert a["u_run"][w] == pytest.approx(U, rel=rel)
+        assert a["v_run"][w] == pytest.approx(V, rel=rel)
+        assert a["n_try"][w] == 0 and a["sum_e"][w] == 0
+
+
+# ---------------------------------------------------------------------------
+# chains in lockstep
+
+def _gpu_chain(p, splits, measure_start, m):
+    coords, acc = abi.alloc_state(p)
+    abi.init_walkers(p, coords, acc, fcc_start=True)
+    t = 0
+    for k in splits:
+        abi.sweep(p, coords, acc, t, k, measure_start, m)
+        t += k
+    torch.cuda.synchronize()
+    return coords.cpu().numpy(), abi.acc_to_numpy(acc)
+
+
+def _oracle_chain(s_, w, n_sweeps, measure_start, m):
+    x = O.fcc_start(s_, w)
+    a = O.walker_init(s_, x)
+    el = O.run_walker(s_, w, x, a, 0, n_sweeps, measure_start, m, record_el=False)
+    return x, a
+
+
+def _compare_walker(xg, ag, xo, ao):
+    assert ag["n_acc"] == ao.n_acc and ag["n_try"] == ao.n_try
+    assert ag["n_samples"] == ao.n_samples and ag["n_sweeps_meas"] == ao.n_sweeps_meas
+    assert np.max(np.abs(xg - xo)) < 1e-9
+    for f in ("sum_e", "sum_e2", "sum_v", "sum_tpb", "sum_tjf", "sum_tf", "sum_vs"):
+        c = "c_" + f[4:]
+        g = ag[f] + ag[c]
+        o = getattr(ao, f) + getattr(ao, c)
+        assert g == pytest.approx(o, rel=1e-10, abs=1e-8), f
+    assert ag["u_run"] == pytest.approx(ao.u_run, rel=1e-10, abs=1e-9)
+    assert ag["v_run"] == pytest.approx(ao.v_run, rel=1e-10, abs=1e-9)
+
+
+def test_lockstep_chain_n108_full_run():
+    """N=108, one walker, 200 equilibration + 1000 measured sweeps, local energy
+    every sweep, split over launches of different lengths."""
+    wl = configs.C1_SMALL_FP64
+    p = abi.params_for(wl)
+    total = wl.equil + wl.measured
+    xg, ag = _gpu_chain(p, [150, 50, 400, 600], wl.equil, wl.m)
+    s_ = osys(wl.n, seed=wl.seed)
+    xo, ao = _oracle_chain(s_, 0, total, wl.equil, wl.m)
+    _compare_walker(xg[0], ag[0], xo, ao)
+    assert ao.n_samples == 1000
+
+
+@pytest.mark.parametrize("threads", [128, 256])
+def test_lockstep_sequential_order_and_threads(threads):
+    n, W = 256, 3
+    p = gparams(n, W, threads=threads, order=1, seed=9, wbase=40)
+    xg, ag = _gpu_chain(p, [7, 5], 4, 2)
+    s_ = osys(n, seed=9, order=1)
+    for w in range(W):
+        xo, ao = _oracle_chain(s_, 40 + w, 12, 4, 2)
+        _compare_walker(xg[w], ag[w], xo, ao)
+
+
+def test_split_launches_bitwise_identical():
+    n, W = 256, 4
+    p = gparams(n, W, seed=3)
+    x1, a1 = _gpu_chain(p, [10], 2, 3)
+    x2, a2 = _gpu_chain(p, [3, 4, 3], 2, 3)
+    assert np.array_equal(x1, x2)
+    assert a1.tobytes() == a2.tobytes()
+
+
+def test_n2048_w512_launch_sampled_walkers():
+    """The benchmark's launch: N=2048, 512 walkers, FP64, five sweeps with a
+    local-energy sample after the fifth; walkers 0, 255 and 511 are replayed by
+    the oracle."""
+    wl = configs.C2_N2048_FP64
+    p = abi.params_for(wl)
+    xg, ag = _gpu_chain(p, [5], 0, 5)
+    s_ = osys(wl.n, seed=wl.seed)
+    picks = [0, 255, 511]
+    res = {}
+
+    def work(w):
+        res[w] = _oracle_chain(s_, w, 5, 0, 5)
+
+    th = [threading.Thread(target=work, args=(w,)) for w in picks]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for w in picks:
+        _compare_walker(xg[w], ag[w], *res[w])
+    # every walker moved and sampled once
+    assert np.all(ag["n_samples"] == 1) and np.all(ag["n_try"] == 5 * wl.n)
+    assert 0.3 < ag["n_acc"].sum() / ag["n_try"].sum() < 0.8
+
+
+# ---------------------------------------------------------------------------
+# ensemble layer
+
+def test_ensemble_matches_stateless_calls():
+    n, W = 108, 2
+    p = gparams(n, W, seed=4)
+    e = abi.Ensemble(p)
+    e.run(5)
+    e.run(10, energy_every=2, measure=True)
+    a = e.acc()
+    x = e.coords()
+    assert e.sweep_index() == 15
+    e.close()
+    xg, ag = _gpu_chain(p, [5, 10], 5, 2)
+    assert np.array_equal(x, xg)
+    assert a.tobytes() == ag.tobytes()
+
+
+def test_ensemble_from_host_coordinates():
+    n, W = 64, 2
+    s_ = osys(n)
+    xs = np.stack([grid_config(n, s_.L, seed=50 + w) for w in range(W)])
+    p = gparams(n, W, seed=2)
+    e = abi.Ensemble(p, init_xyz=xs)
+    a0 = e.acc()
+    for w in range(W):
+        U, V = O.totals(s_, xs[w])
+        assert a0["u_run"][w] == pytest.approx(U, rel=1e-12)
+        assert a0["v_run"][w] == pytest.approx(V, rel=1e-12)
+    bad = xs.copy()
+    bad[0, 0, 0] = s_.L + 1.0
+    with pytest.raises(abi.HevmcError):
+        abi.Ensemble(p, init_xyz=bad)
+    e.close()
