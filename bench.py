@@ -1,0 +1,199 @@
+"""Throughput of the VMC hot path on one MI355X.
+
+Workload (default): liquid 4He, N=2048 atoms per walker (fcc 8x8x8 start),
+density 0.02186 / A^3, b = 1.15 sigma, 512 walkers, FP64, Gaussian moves with
+~50% acceptance, local energy every 5 sweeps.  One step = one launch of the
+sweep kernel: 5 sweeps of every walker (N micro-updates each, the O(N) pair loop
+per micro-update) followed by one O(N^2) local-energy evaluation per walker.
+Warm-up steps double as equilibration; measurement starts with the first timed
+step.
+
+Prints one JSON line: moves/s, the roofline of the sweep kernel (vector ALU,
+FP64) from per-launch HIP events, and the CPU oracle timed on the host cores on
+a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FLOPs per unit of work, counted from the formulas (add, mul = 1,
+# fused multiply-add = 2; sqrt, reciprocals, rounding and exp count zero, so
+# fractions of peak are lower bounds):
+#   distance of one pair (difference, minimum image, r^2)          17
+#   u given r^-1, (L-r)^-1                                          11
+#   V given r, r^-2 (exponent, dispersion series, damping, scale)   18
+# plain sweep, per pair term: u and V at the old and the new position and the
+#   two differences accumulated                          2 (17+11+18) + 4 = 96
+# row-sum sweep, per pair: forward half (distance, u, sum)           29
+#   plus, for an accepted move: old u and V, new V, row update, dV   86
+# local energy, per unordered pair: distance, u, u', u'', V, gradient and
+#   Laplacian terms for both atoms, V and U sums                     70
+FLOP_PLAIN_PAIR = 96
+FLOP_ROWS_FORWARD = 29
+FLOP_ROWS_ACCEPT = 86
+FLOP_ENERGY_PAIR = 70
+PEAK = {"f64": 78.6, "f32": 157.3}   # MI355X vector TFLOP/s (published)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="he4_n2048_w512_fp64")
+    ap.add_argument("--sweeps-per-step", type=int, default=5)
+    ap.add_argument("--threads", type=int, default=0, help="threads per walker (0 = library choice)")
+    ap.add_argument("--variant", type=int, default=0, help="sweep variant: 0 auto, 1 plain, 2 row sums")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=5)
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, sweeps):
+    """The oracle as it stands, one walker per host thread, `sweeps` sweeps of
+    each with one local-energy sample (the step's work mix), from the fcc
+    start."""
+    import numpy as np
+
+    import oracle as O
+    from paper_1312_1282_amd import configs
+
+    cores = min(os.cpu_count() or 1, 16)
+    W = cores
+    s_ = O.system(wl.n, O.box_side(wl.n, wl.density, wl.precision == configs.FP32), wl.b,
+                  hbar2_over_m=configs.HBAR2_OVER_M, step_sigma=wl.step_sigma, seed=wl.seed)
+    xyz = np.stack([O.fcc_start(s_, w) for w in range(W)])
+    accs = (O.Walker * W)(*[O.walker_init(s_, xyz[w]) for w in range(W)])
+    t0 = time.perf_counter()
+    O.run_walkers(s_, 0, xyz, accs, 0, sweeps, 0, sweeps, cores)
+    dt = time.perf_counter() - t0
+    moves = W * wl.n * sweeps
+    return {
+        "value": moves / dt,
+        "unit": "moves/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"{W} walkers x {sweeps} sweeps of N={wl.n} (+1 local energy each), one walker per thread, "
+                  f"{dt:.1f} s wall",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(walkers are independent chains: G GPUs would each run W/G walkers of the same kernel).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1312_1282_amd import abi, configs
+
+    wl = configs.ALL[args.workload]
+    p = abi.params_for(wl, threads=args.threads, variant=args.variant)
+    dtype = "f32" if wl.precision == configs.FP32 else "f64"
+    torch.cuda.set_device(0)
+    coords, acc = abi.alloc_state(p)
+    rows = abi.alloc_rows(p)
+    abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
+    S = args.sweeps_per_step
+    m = wl.m
+    t = 0
+    for _ in range(args.warmup):
+        abi.sweep(p, coords, acc, t, S, abi.NO_MEASURE, 0, rows=rows)
+        t += S
+    torch.cuda.synchronize()
+    # fresh accumulators for the measured part (running totals kept)
+    mstart = t
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        abi.sweep(p, coords, acc, t, S, mstart, m, stream=stream, rows=rows)
+        ev[k][1].record(stream)
+        t += S
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall0
+    launch_ms = np.array([a.elapsed_time(b) for a, b in ev])
+
+    a = abi.acc_to_numpy(acc)
+    moves_per_step = wl.walkers * wl.n * S
+    value = moves_per_step * args.steps / wall
+    samples_per_step = wl.walkers * (S // m if m > 0 else 0)
+    acc_rate = float(a["n_acc"].sum() / max(a["n_try"].sum(), 1))
+    rows_variant = abi.plan_uses_rows(p)
+    if rows_variant:
+        pair_flop = FLOP_ROWS_FORWARD + acc_rate * FLOP_ROWS_ACCEPT
+    else:
+        pair_flop = FLOP_PLAIN_PAIR
+    flop_launch = (moves_per_step * (wl.n - 1) * pair_flop
+                   + samples_per_step * (wl.n * (wl.n - 1) // 2) * FLOP_ENERGY_PAIR)
+    avg_s = float(launch_ms.mean()) * 1e-3
+    achieved = flop_launch / avg_s / 1e12
+
+    a = abi.acc_to_numpy(acc)
+    ns = np.maximum(a["n_samples"], 1)
+    e_w = (a["sum_e"] + a["c_e"]) / ns / wl.n
+    physics = {
+        "E_per_atom_K": float(e_w.mean()),
+        "E_se_K": float(e_w.std(ddof=1) / np.sqrt(len(e_w))) if len(e_w) > 1 else None,
+        "acceptance": acc_rate,
+        "samples_per_walker": int(a["n_samples"][0]),
+    }
+
+    line = {
+        "metric": "single-particle Metropolis moves/s at N=2048; served p50/p99 time-to-1mK",
+        "value": value,
+        "unit": "moves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic: fcc-started liquid 4He walkers, equilibrated during warm-up",
+        "config": {
+            "workload": wl.name,
+            "n_atoms": wl.n,
+            "walkers": wl.walkers,
+            "density_per_A3": wl.density,
+            "b_A": wl.b,
+            "step_sigma_A": wl.step_sigma,
+            "sweeps_per_step": S,
+            "energy_every": m,
+            "threads_per_walker": p.threads or None,
+            "variant": "rows" if rows_variant else "plain",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK[dtype],
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK[dtype],
+            "traffic": None,
+            "kernel": "k_sweep",
+            "launch_ms_avg": float(launch_ms.mean()),
+            "flop_per_launch": flop_launch,
+        },
+        "physics": physics,
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(wl, args.cpu_sweeps)
+        cb["gpu_over_cpu"] = value / cb["value"]
+        line["cpu_baseline"] = cb
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

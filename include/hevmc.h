@@ -62,6 +62,19 @@ typedef enum {
     HEVMC_SELECT_SEQUENTIAL = 1  /* s = k, the micro-step index                          */
 } hevmc_order;
 
+/* How the sweep forms the Eq. (7) sums (same Markov chain either way, up to
+ * rounding).  PLAIN evaluates u and V at the old and the new position of the
+ * moved atom for every trial move.  ROWS keeps each atom's row sum
+ * R_i = sum_{j != i} u(r_ij) (FP64, in LDS; refreshed by every local-energy
+ * pass) and evaluates only u at the new position per trial move; the old
+ * position's terms, the row updates and dV are formed only for accepted moves.
+ * ROWS needs N <= 8 x threads and 8 N more bytes of LDS per walker. */
+typedef enum {
+    HEVMC_VARIANT_AUTO = 0,      /* ROWS when it fits, else PLAIN */
+    HEVMC_VARIANT_PLAIN = 1,
+    HEVMC_VARIANT_ROWS = 2
+} hevmc_variant;
+
 /* Parameters of one ensemble of independent walkers (Markov chains). */
 typedef struct {
     int32_t n;               /* atoms per walker N, >= 2                                  */
@@ -76,6 +89,7 @@ typedef struct {
     uint32_t walker_id_base; /* walker w uses Philox walker id walker_id_base + w         */
     int32_t threads;         /* threads per walker: 0 = library choice, else 128, 256,
                                 512 or 1024                                                */
+    int32_t variant;         /* hevmc_variant                                             */
 } hevmc_params;
 
 /* Per-walker running state and accumulators, in device memory ([W] array).
@@ -108,10 +122,12 @@ hevmc_status hevmc_footprint(const hevmc_params *p, size_t *lds_bytes_per_walker
 /* Start walkers.  If fcc_start != 0, first writes the fcc start with a
  * deterministic jitter of 1e-3 lattice constants (device coords [W][3][N]);
  * otherwise coords must already hold valid positions.  Then sets u_run, v_run
- * of every walker from a full O(N^2) evaluation and zeroes all accumulators.
+ * of every walker from a full O(N^2) evaluation, zeroes all accumulators and,
+ * if rows is not NULL, fills rows ([W][N] doubles, device) with each atom's
+ * row sum sum_{j != i} u(r_ij) for later hevmc_sweep calls.
  * coords, acc: device.  Asynchronous on stream. */
 hevmc_status hevmc_init_walkers(const hevmc_params *p, void *coords, hevmc_walker_acc *acc,
-                                int32_t fcc_start, void *stream);
+                                double *rows, int32_t fcc_start, void *stream);
 
 /* The hot path: sweeps t = sweep0 .. sweep0+n_sweeps-1 of all W walkers
  * (Sec. 5.1 workflow; one sweep = N micro-updates, a "macroupdate" of Sec. 4.1).
@@ -122,9 +138,14 @@ hevmc_status hevmc_init_walkers(const hevmc_params *p, void *coords, hevmc_walke
  * energy_every = m > 0 and (t - measure_start + 1) % m == 0 the local energy of
  * the configuration is evaluated, added to the accumulators, and u_run, v_run
  * are reset to its fresh totals.  Pass measure_start = 0xFFFFFFFF for
- * equilibration only.  coords, acc: device, updated in place.  Requires
- * sweep0 + n_sweeps <= 0xFFFFFFFF.  Asynchronous on stream. */
-hevmc_status hevmc_sweep(const hevmc_params *p, void *coords, hevmc_walker_acc *acc,
+ * equilibration only.  coords, acc: device, updated in place.  rows: NULL or
+ * a device [W][N] double buffer that keeps the row sums of the ROWS variant
+ * between calls (filled by hevmc_init_walkers or a previous hevmc_sweep on the
+ * same walkers); the kernel checks sum_i R_i = 2 u_run and recomputes the rows
+ * when the buffer is NULL or disagrees, an O(N^2) pass per walker.  Ignored by
+ * the PLAIN variant.  Requires sweep0 + n_sweeps <= 0xFFFFFFFF.  Asynchronous
+ * on stream. */
+hevmc_status hevmc_sweep(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
                          uint32_t sweep0, int32_t n_sweeps, uint32_t measure_start,
                          int32_t energy_every, void *stream);
 

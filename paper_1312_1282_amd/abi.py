@@ -16,6 +16,9 @@ FP64 = 0
 FP32 = 1
 SELECT_RANDOM = 0
 SELECT_SEQUENTIAL = 1
+VARIANT_AUTO = 0
+VARIANT_PLAIN = 1
+VARIANT_ROWS = 2
 NO_MEASURE = 0xFFFFFFFF
 
 STATUS = {0: "HEVMC_OK", -1: "HEVMC_EINVAL", -2: "HEVMC_ENOMEM", -3: "HEVMC_ENOFIT",
@@ -41,6 +44,7 @@ class Params(C.Structure):
         ("seed", C.c_uint64),
         ("walker_id_base", C.c_uint32),
         ("threads", C.c_int32),
+        ("variant", C.c_int32),
     ]
 
 
@@ -82,8 +86,8 @@ def lib():
         sig = {
             "hevmc_box": [P, C.POINTER(C.c_double)],
             "hevmc_footprint": [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)],
-            "hevmc_init_walkers": [P, vp, vp, C.c_int32, vp],
-            "hevmc_sweep": [P, vp, vp, C.c_uint32, C.c_int32, C.c_uint32, C.c_int32, vp],
+            "hevmc_init_walkers": [P, vp, vp, vp, C.c_int32, vp],
+            "hevmc_sweep": [P, vp, vp, vp, C.c_uint32, C.c_int32, C.c_uint32, C.c_int32, vp],
             "hevmc_local_energy": [P, vp, vp, vp],
             "hevmc_move_delta": [P, vp, vp, vp, vp, vp],
             "hevmc_draw_moves": [P, C.c_uint32, vp, vp, vp, vp],
@@ -113,9 +117,10 @@ def _check(code):
 
 
 def make_params(n, n_walkers, precision=FP64, density=0.02186, b=1.15 * 2.556, hbar2_over_m=12.1194,
-                step_sigma=0.63, seed=1, walker_id_base=0, threads=0, order=SELECT_RANDOM):
+                step_sigma=0.63, seed=1, walker_id_base=0, threads=0, order=SELECT_RANDOM, variant=VARIANT_AUTO):
     return Params(int(n), int(n_walkers), int(precision), int(order), float(density), float(b),
-                  float(hbar2_over_m), float(step_sigma), int(seed), int(walker_id_base), int(threads))
+                  float(hbar2_over_m), float(step_sigma), int(seed), int(walker_id_base), int(threads),
+                  int(variant))
 
 
 def params_for(workload, **over):
@@ -136,6 +141,13 @@ def footprint(p):
     lds, hbm = C.c_size_t(), C.c_size_t()
     _check(lib().hevmc_footprint(C.byref(p), C.byref(lds), C.byref(hbm)))
     return lds.value, hbm.value
+
+
+def plan_uses_rows(p):
+    """True if the library runs the row-sum variant of the sweep for p."""
+    lds, _ = footprint(p)
+    tsz = 4 if p.precision == FP32 else 8
+    return lds > 3 * p.n * tsz
 
 
 # ---- torch-facing helpers -------------------------------------------------
@@ -177,16 +189,28 @@ def alloc_state(p, device="cuda"):
     return coords, acc
 
 
-def init_walkers(p, coords, acc, fcc_start=True, stream=None):
+def alloc_rows(p, device="cuda"):
+    """Device buffer [W,N] float64 for the per-atom row sums kept between sweeps."""
+    torch = _torch()
+    return torch.zeros((p.n_walkers, p.n), dtype=torch.float64, device=device)
+
+
+def _rows_ptr(p, rows):
+    if rows is None:
+        return None
+    return _ptr(rows, _torch().float64, (p.n_walkers, p.n), "rows")
+
+
+def init_walkers(p, coords, acc, fcc_start=True, stream=None, rows=None):
     _check(lib().hevmc_init_walkers(C.byref(p), _ptr(coords, coord_dtype(p), (p.n_walkers, 3, p.n), "coords"),
-                                    _ptr(acc, None, (p.n_walkers, ACC_BYTES), "acc"), int(bool(fcc_start)),
-                                    _stream(stream)))
+                                    _ptr(acc, None, (p.n_walkers, ACC_BYTES), "acc"), _rows_ptr(p, rows),
+                                    int(bool(fcc_start)), _stream(stream)))
 
 
-def sweep(p, coords, acc, sweep0, n_sweeps, measure_start=NO_MEASURE, energy_every=0, stream=None):
+def sweep(p, coords, acc, sweep0, n_sweeps, measure_start=NO_MEASURE, energy_every=0, stream=None, rows=None):
     _check(lib().hevmc_sweep(C.byref(p), _ptr(coords, coord_dtype(p), (p.n_walkers, 3, p.n), "coords"),
-                             _ptr(acc, None, (p.n_walkers, ACC_BYTES), "acc"), int(sweep0), int(n_sweeps),
-                             int(measure_start), int(energy_every), _stream(stream)))
+                             _ptr(acc, None, (p.n_walkers, ACC_BYTES), "acc"), _rows_ptr(p, rows), int(sweep0),
+                             int(n_sweeps), int(measure_start), int(energy_every), _stream(stream)))
 
 
 def local_energy(p, coords, out, stream=None):

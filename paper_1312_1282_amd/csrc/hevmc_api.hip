@@ -35,8 +35,9 @@ hevmc_status hip_fail(hipError_t e, const char *what)
     return fail(HEVMC_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
 }
 
-// Static LDS of the kernels: partial sums, at most 16 waves x (2x2 + 4) doubles.
-constexpr size_t kStaticLds = 16 * 8 * sizeof(double);
+// Static LDS of the kernels (partial sums: (2x2 + 4) doubles per wave plus two),
+// with a margin.
+size_t static_lds(int threads) { return (size_t)(threads / 64) * 8 * sizeof(double) + 64; }
 
 struct DeviceLimits {
     int cus = 0;
@@ -95,6 +96,8 @@ hevmc_status check_params(const hevmc_params *p)
         return fail(HEVMC_EINVAL, "step_sigma = %g must be finite and > 0", p->step_sigma);
     if (p->threads != 0 && p->threads != 128 && p->threads != 256 && p->threads != 512 && p->threads != 1024)
         return fail(HEVMC_EINVAL, "threads = %d must be 0, 128, 256, 512 or 1024", p->threads);
+    if (p->variant < HEVMC_VARIANT_AUTO || p->variant > HEVMC_VARIANT_ROWS)
+        return fail(HEVMC_EINVAL, "variant = %d is not a hevmc_variant", p->variant);
     return HEVMC_OK;
 }
 
@@ -116,6 +119,16 @@ size_t lds_needed(const hevmc_params *p)
     return (size_t)3 * (size_t)p->n * (p->precision == HEVMC_FP32 ? sizeof(float) : sizeof(double));
 }
 
+size_t rows_lds_bytes(const hevmc_params *p)
+{
+    const size_t tsz = p->precision == HEVMC_FP32 ? sizeof(float) : sizeof(double);
+    return rows_lds_offset(p->n, tsz) + (size_t)p->n * sizeof(double);
+}
+
+// Launch plan: threads per walker, sweep variant and the dynamic LDS request.
+// The request is padded so that each compute unit holds r walkers, r the
+// largest divisor of ceil(W / CUs) whose walkers fit in its LDS: the walkers
+// are then spread evenly over the chip, in equal rounds.
 hevmc_status plan(const hevmc_params *p, void *stream, Launch &L)
 {
     hevmc_status st = check_params(p);
@@ -124,21 +137,33 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L)
     DeviceLimits d;
     if ((st = device_limits(d)) != HEVMC_OK)
         return st;
-    const size_t need = lds_needed(p);
-    const size_t max_dyn = d.lds_per_block > kStaticLds ? d.lds_per_block - kStaticLds : 0;
-    if (need > max_dyn)
+    const int threads = p->threads ? p->threads : default_threads(p->n);
+    const size_t stat = static_lds(threads);
+    const size_t max_dyn = d.lds_per_block > stat ? d.lds_per_block - stat : 0;
+    const size_t need_plain = lds_needed(p);
+    const size_t need_rows = rows_lds_bytes(p);
+    if (need_plain > max_dyn)
         return fail(HEVMC_ENOFIT, "walker of %d atoms needs %zu B of LDS; a workgroup can have %zu B", p->n,
-                    need, max_dyn);
-    // Pad the LDS request so that no compute unit holds more than
-    // ceil(W / CUs) walkers: the walkers are then spread evenly over the chip.
+                    need_plain, max_dyn);
+    const bool rows_ok = p->n <= kRowsPerLane * threads && need_rows <= max_dyn;
+    if (p->variant == HEVMC_VARIANT_ROWS && !rows_ok)
+        return fail(HEVMC_ENOFIT, "row-sum sweep needs N <= %d x threads and %zu B of LDS per walker",
+                    kRowsPerLane, need_rows);
+    const bool use_rows = p->variant == HEVMC_VARIANT_ROWS || (p->variant == HEVMC_VARIANT_AUTO && rows_ok);
+    const size_t need = use_rows ? need_rows : need_plain;
     size_t lds = need;
     const int per_cu = (p->n_walkers + d.cus - 1) / d.cus;
-    if (per_cu >= 1 && d.lds_per_cu > 0) {
-        size_t even = d.lds_per_cu / (size_t)per_cu;
-        even = even > kStaticLds + 256 ? even - kStaticLds - 256 : 0;
+    for (int r = per_cu; r >= 1; --r) {
+        if (per_cu % r != 0)
+            continue;
+        if ((size_t)r * (need + stat) > d.lds_per_cu)
+            continue;
+        size_t even = d.lds_per_cu / (size_t)r;
+        even = even > stat + 128 ? even - stat - 128 : 0;
         even &= ~(size_t)255;
         if (even > lds)
             lds = even < max_dyn ? even : max_dyn;
+        break;
     }
     const double Ld = box_side(p);
     const double h = 0.5 * Ld;
@@ -163,8 +188,9 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L)
     k.c5f = (float)k.c5;
     k.u0f = (float)k.u0;
     L.p.n_walkers_grid = p->n_walkers;
-    L.threads = p->threads ? p->threads : default_threads(p->n);
+    L.threads = threads;
     L.fp32 = p->precision == HEVMC_FP32;
+    L.rows = use_rows;
     L.lds_bytes = lds;
     L.stream = (hipStream_t)stream;
     return HEVMC_OK;
@@ -200,15 +226,18 @@ extern "C" hevmc_status hevmc_footprint(const hevmc_params *p, size_t *lds_bytes
 {
     Launch L;
     hevmc_status st = plan(p, nullptr, L);
+    if (st != HEVMC_OK)
+        return st;
     if (lds_bytes_per_walker)
-        *lds_bytes_per_walker = check_params(p) == HEVMC_OK ? lds_needed(p) : 0;
-    if (hbm_bytes && check_params(p) == HEVMC_OK)
-        *hbm_bytes = lds_needed(p) * (size_t)p->n_walkers + sizeof(hevmc_walker_acc) * (size_t)p->n_walkers;
-    return st;
+        *lds_bytes_per_walker = L.rows ? rows_lds_bytes(p) : lds_needed(p);
+    if (hbm_bytes)
+        *hbm_bytes = (lds_needed(p) + sizeof(hevmc_walker_acc) + (size_t)p->n * sizeof(double)) *
+                     (size_t)p->n_walkers;
+    return HEVMC_OK;
 }
 
 extern "C" hevmc_status hevmc_init_walkers(const hevmc_params *p, void *coords, hevmc_walker_acc *acc,
-                                           int32_t fcc_start, void *stream)
+                                           double *rows, int32_t fcc_start, void *stream)
 {
     Launch L;
     hevmc_status st = plan(p, stream, L);
@@ -218,11 +247,12 @@ extern "C" hevmc_status hevmc_init_walkers(const hevmc_params *p, void *coords, 
         return fail(HEVMC_EINVAL, "coords and acc must be device pointers");
     int nc;
     fcc_cells(p->n, nc);
-    return launched(launch_init(L, coords, acc, fcc_start ? 1 : 0, nc, L.k.L / nc), "init kernel launch");
+    return launched(launch_init(L, coords, acc, rows, fcc_start ? 1 : 0, nc, L.k.L / nc), "init kernel launch");
 }
 
-extern "C" hevmc_status hevmc_sweep(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, uint32_t sweep0,
-                                    int32_t n_sweeps, uint32_t measure_start, int32_t energy_every, void *stream)
+extern "C" hevmc_status hevmc_sweep(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
+                                    uint32_t sweep0, int32_t n_sweeps, uint32_t measure_start, int32_t energy_every,
+                                    void *stream)
 {
     Launch L;
     hevmc_status st = plan(p, stream, L);
@@ -238,7 +268,7 @@ extern "C" hevmc_status hevmc_sweep(const hevmc_params *p, void *coords, hevmc_w
         return fail(HEVMC_EINVAL, "sweep counter would pass 2^32 - 1");
     if (n_sweeps == 0)
         return HEVMC_OK;
-    return launched(launch_sweep(L, coords, acc, sweep0, n_sweeps, measure_start, energy_every),
+    return launched(launch_sweep(L, coords, acc, rows, sweep0, n_sweeps, measure_start, energy_every),
                     "sweep kernel launch");
 }
 
@@ -287,6 +317,7 @@ struct hevmc_ensemble {
     hipStream_t stream;
     void *coords;
     hevmc_walker_acc *acc;
+    double *rows;       // row sums kept between launches (owned), or null
     bool owns;
     uint32_t sweep;
     uint32_t mstart;
@@ -353,15 +384,18 @@ extern "C" hevmc_status hevmc_create(const hevmc_params *p, const double *init_x
         return fail(HEVMC_ENOMEM, "hipMalloc of %zu B for coordinates failed", cbytes);
     }
     he = hipMalloc((void **)&e->acc, sizeof(hevmc_walker_acc) * (size_t)p->n_walkers);
+    if (he == hipSuccess)
+        he = hipMalloc((void **)&e->rows, sizeof(double) * (size_t)p->n * (size_t)p->n_walkers);
     if (he != hipSuccess) {
         (void)hipFree(e->coords);
+        (void)hipFree(e->acc);
         delete e;
-        return fail(HEVMC_ENOMEM, "hipMalloc of accumulators failed");
+        return fail(HEVMC_ENOMEM, "hipMalloc of walker state failed");
     }
     if (init_xyz)
         st = upload_coords(p, init_xyz, count, e->coords, e->stream);
     if (st == HEVMC_OK)
-        st = hevmc_init_walkers(p, e->coords, e->acc, init_xyz ? 0 : 1, stream);
+        st = hevmc_init_walkers(p, e->coords, e->acc, e->rows, init_xyz ? 0 : 1, stream);
     if (st == HEVMC_OK) {
         he = hipStreamSynchronize(e->stream);
         if (he != hipSuccess)
@@ -393,10 +427,11 @@ extern "C" hevmc_status hevmc_create_on(const hevmc_params *p, void *dev_coords,
     e->stream = (hipStream_t)stream;
     e->coords = dev_coords;
     e->acc = dev_acc;
+    e->rows = nullptr;
     e->owns = false;
     e->sweep = 0;
     e->mstart = 0xFFFFFFFFu;
-    st = hevmc_init_walkers(p, dev_coords, dev_acc, 0, stream);
+    st = hevmc_init_walkers(p, dev_coords, dev_acc, nullptr, 0, stream);
     if (st != HEVMC_OK) {
         delete e;
         return st;
@@ -414,7 +449,8 @@ extern "C" hevmc_status hevmc_run(hevmc_ensemble *e, int32_t n_sweeps, int32_t e
     if (measure && e->mstart == 0xFFFFFFFFu)
         e->mstart = e->sweep;
     const uint32_t mstart = measure ? e->mstart : 0xFFFFFFFFu;
-    hevmc_status st = hevmc_sweep(&e->p, e->coords, e->acc, e->sweep, n_sweeps, mstart, energy_every, e->stream);
+    hevmc_status st =
+        hevmc_sweep(&e->p, e->coords, e->acc, e->rows, e->sweep, n_sweeps, mstart, energy_every, e->stream);
     if (st == HEVMC_OK)
         e->sweep += (uint32_t)n_sweeps;
     return st;
@@ -488,6 +524,7 @@ extern "C" hevmc_status hevmc_destroy(hevmc_ensemble *e)
             st = hip_fail(he, "synchronise before free");
         (void)hipFree(e->coords);
         (void)hipFree(e->acc);
+        (void)hipFree(e->rows);
     }
     delete e;
     return st;

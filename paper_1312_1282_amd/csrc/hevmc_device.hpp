@@ -44,6 +44,8 @@ constexpr double D = 1.4826;
 constexpr double inv_rm = 1.0 / rm;
 constexpr double rm2 = rm * rm;
 constexpr double Drm = D * rm;        // D / x = Drm / r
+constexpr double beta_rm2 = beta / (rm * rm);   // -alpha x + beta x^2 = beta_rm2 r^2 - alpha_rm r
+constexpr double alpha_rm = alpha / rm;
 }  // namespace az
 
 // --------------------------------------------------------------------------
@@ -103,30 +105,117 @@ __device__ __forceinline__ double min_image(double d, const KParams &p) { return
 __device__ __forceinline__ float min_image(float d, const KParams &p) { return d - p.Lf * rintf(d * p.invLf); }
 
 // --------------------------------------------------------------------------
+// FP64 elementary functions for the pair loop.  Division, sqrt and exp from the
+// device math library are correctly rounded or within an ulp but expand to long
+// instruction sequences; these use the hardware estimates with Newton steps.
+
+// 1/x: hardware reciprocal estimate refined by two Newton steps
+// (y <- y + y (1 - x y)); relative error at the rounding level.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+// 1/sqrt(x): hardware estimate refined by two Newton steps
+// (y <- y + (y/2)(1 - x y^2)).
+__device__ __forceinline__ double rsq_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * y;
+    double e = fma(-(x * y), y, 1.0);
+    y = fma(h, e, y);
+    h = 0.5 * y;
+    e = fma(-(x * y), y, 1.0);
+    return fma(h, e, y);
+}
+
+// e^a for a <= 0 (both exponentials of the potential have non-positive
+// arguments).  Cody-Waite reduction a = k ln2 + f, |f| <= ln2/2, with the
+// two-part ln2 of fdlibm (its high part has trailing zero bits, so k*ln2_hi is
+// exact), e^f by its Taylor series to degree 12 (truncation < 2e-16 relative),
+// scaled by 2^k.  Arguments below -708 are clamped there (the result, ~3e-308,
+// is zero for every sum it enters).
+__device__ __forceinline__ double exp_neg(double a)
+{
+    a = fmax(a, -708.0);
+    const double k = rint(a * 1.4426950408889634);
+    double f = fma(-k, 6.93147180369123816490e-01, a);
+    f = fma(-k, 1.90821492927058770002e-10, f);
+    double q = 2.08767569878680989792e-09;        // 1/12!
+    q = fma(q, f, 2.50521083854417187751e-08);    // 1/11!
+    q = fma(q, f, 2.75573192239858906526e-07);    // 1/10!
+    q = fma(q, f, 2.75573192239858906526e-06);    // 1/9!
+    q = fma(q, f, 2.48015873015873015873e-05);    // 1/8!
+    q = fma(q, f, 1.98412698412698412698e-04);    // 1/7!
+    q = fma(q, f, 1.38888888888888888889e-03);    // 1/6!
+    q = fma(q, f, 8.33333333333333333333e-03);    // 1/5!
+    q = fma(q, f, 4.16666666666666666667e-02);    // 1/4!
+    q = fma(q, f, 1.66666666666666666667e-01);    // 1/3!
+    q = fma(q, f, 0.5);
+    q = fma(q, f, 1.0);
+    q = fma(q, f, 1.0);
+    return ldexp(q, (int)k);
+}
+
+// --------------------------------------------------------------------------
 // Pair terms at squared min-image distance r2 (Eqs. (8), (9); HFD-B(HE)).
-// u and V are zero beyond the inclusive cutoff L/2; callers mask i == s.
+// u and V are zero beyond the inclusive cutoff L/2; callers mask i == s
+// (r2 = 0 gives non-finite terms that the mask discards).
 
 // FP64: u(r) and V(r).
 __device__ __forceinline__ void pair_uv(const KParams &p, double r2, double &u, double &v)
 {
-    const double r = sqrt(r2);
-    const double ri = 1.0 / r;
-    const double rpi = 1.0 / (p.L - r);
+    const double ri = rsq_nr(r2);
+    const double r = r2 * ri;
+    const double rpi = rcp_nr(p.L - r);
     const double ri2 = ri * ri, rpi2 = rpi * rpi;
-    const double uu = p.c5 * (ri2 * ri2 * ri + rpi2 * rpi2 * rpi) + p.u0;
-    const double x = r * az::inv_rm;
-    const double rep = az::A * exp(x * (az::beta * x - az::alpha));
-    const double y = az::rm2 * (ri2);                 // x^-2
-    const double disp = y * y * y * (az::C6 + y * (az::C8 + y * az::C10));
+    const double uu = fma(p.c5, fma(ri2 * ri2, ri, rpi2 * rpi2 * rpi), p.u0);
+    const double rep = az::A * exp_neg(fma(az::beta_rm2, r2, -(az::alpha_rm * r)));
+    const double y = az::rm2 * ri2;                   // x^-2
+    const double y2 = y * y;
+    const double disp = y2 * y * fma(y, fma(y, az::C10, az::C8), az::C6);
     double F = 1.0;
-    if (x < az::D) {
-        const double q = az::Drm * ri - 1.0;
-        F = exp(-(q * q));
+    if (r < az::Drm) {
+        const double q = fma(az::Drm, ri, -1.0);
+        F = exp_neg(-(q * q));
     }
-    const double vv = az::eps * (rep - F * disp);
+    const double vv = az::eps * fma(-F, disp, rep);
     const bool in = r2 <= p.h2;
     u = in ? uu : 0.0;
     v = in ? vv : 0.0;
+}
+
+// FP64: u(r) alone (the forward half of a micro-update needs only ln psi).
+__device__ __forceinline__ double pair_u(const KParams &p, double r2)
+{
+    const double ri = rsq_nr(r2);
+    const double r = r2 * ri;
+    const double rpi = rcp_nr(p.L - r);
+    const double ri2 = ri * ri, rpi2 = rpi * rpi;
+    const double uu = fma(p.c5, fma(ri2 * ri2, ri, rpi2 * rpi2 * rpi), p.u0);
+    return r2 <= p.h2 ? uu : 0.0;
+}
+
+// FP64: V(r) alone.
+__device__ __forceinline__ double pair_v(const KParams &p, double r2)
+{
+    const double ri = rsq_nr(r2);
+    const double r = r2 * ri;
+    const double rep = az::A * exp_neg(fma(az::beta_rm2, r2, -(az::alpha_rm * r)));
+    const double y = az::rm2 * (ri * ri);
+    const double y2 = y * y;
+    const double disp = y2 * y * fma(y, fma(y, az::C10, az::C8), az::C6);
+    double F = 1.0;
+    if (r < az::Drm) {
+        const double q = fma(az::Drm, ri, -1.0);
+        F = exp_neg(-(q * q));
+    }
+    const double vv = az::eps * fma(-F, disp, rep);
+    return r2 <= p.h2 ? vv : 0.0;
 }
 
 // FP32 form: same terms in single precision with the hardware reciprocal,
@@ -155,6 +244,33 @@ __device__ __forceinline__ void pair_uv(const KParams &p, float r2, float &u, fl
     v = in ? vv : 0.0f;
 }
 
+__device__ __forceinline__ float pair_u(const KParams &p, float r2)
+{
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * ri;
+    const float rpi = __builtin_amdgcn_rcpf(p.Lf - r);
+    const float ri2 = ri * ri, rpi2 = rpi * rpi;
+    const float uu = p.c5f * (ri2 * ri2 * ri + rpi2 * rpi2 * rpi) + p.u0f;
+    return r2 <= p.h2f ? uu : 0.0f;
+}
+
+__device__ __forceinline__ float pair_v(const KParams &p, float r2)
+{
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * ri;
+    const float x = r * (float)az::inv_rm;
+    const float rep = (float)az::A * fexp(x * ((float)az::beta * x - (float)az::alpha));
+    const float y = (float)az::rm2 * (ri * ri);
+    const float disp = y * y * y * ((float)az::C6 + y * ((float)az::C8 + y * (float)az::C10));
+    float F = 1.0f;
+    if (x < (float)az::D) {
+        const float q = (float)az::Drm * ri - 1.0f;
+        F = fexp(-(q * q));
+    }
+    const float vv = (float)az::eps * (rep - F * disp);
+    return r2 <= p.h2f ? vv : 0.0f;
+}
+
 // Terms of the local energy of one ordered pair: u, V, u'/r (the gradient of
 // ln psi is sum u'/r d) and u'' + 2u'/r (the Laplacian term), zero beyond L/2.
 // u' = -5 c5 (r^-6 - (L-r)^-6), u'' = 30 c5 (r^-7 + (L-r)^-7).
@@ -164,31 +280,31 @@ struct ETerms {
 
 __device__ __forceinline__ void pair_energy(const KParams &p, double r2, ETerms &e)
 {
-    const double r = sqrt(r2);
-    const double ri = 1.0 / r;
-    const double rpi = 1.0 / (p.L - r);
+    const double ri = rsq_nr(r2);
+    const double r = r2 * ri;
+    const double rpi = rcp_nr(p.L - r);
     const double ri2 = ri * ri, rpi2 = rpi * rpi;
     const double ri5 = ri2 * ri2 * ri, rpi5 = rpi2 * rpi2 * rpi;
     const double ri6 = ri5 * ri, rpi6 = rpi5 * rpi;
-    const double uu = p.c5 * (ri5 + rpi5) + p.u0;
+    const double uu = fma(p.c5, ri5 + rpi5, p.u0);
     const double du = -5.0 * p.c5 * (ri6 - rpi6);
-    const double d2u = 30.0 * p.c5 * (ri6 * ri + rpi6 * rpi);
-    const double x = r * az::inv_rm;
-    const double rep = az::A * exp(x * (az::beta * x - az::alpha));
+    const double d2u = 30.0 * p.c5 * fma(ri6, ri, rpi6 * rpi);
+    const double rep = az::A * exp_neg(fma(az::beta_rm2, r2, -(az::alpha_rm * r)));
     const double y = az::rm2 * ri2;
-    const double disp = y * y * y * (az::C6 + y * (az::C8 + y * az::C10));
+    const double y2 = y * y;
+    const double disp = y2 * y * fma(y, fma(y, az::C10, az::C8), az::C6);
     double F = 1.0;
-    if (x < az::D) {
-        const double q = az::Drm * ri - 1.0;
-        F = exp(-(q * q));
+    if (r < az::Drm) {
+        const double q = fma(az::Drm, ri, -1.0);
+        F = exp_neg(-(q * q));
     }
-    const double vv = az::eps * (rep - F * disp);
+    const double vv = az::eps * fma(-F, disp, rep);
     const double dur = du * ri;
     const bool in = r2 <= p.h2;
     e.u = in ? uu : 0.0;
     e.v = in ? vv : 0.0;
     e.dur = in ? dur : 0.0;
-    e.lap = in ? d2u + 2.0 * dur : 0.0;
+    e.lap = in ? fma(2.0, dur, d2u) : 0.0;
 }
 
 __device__ __forceinline__ void pair_energy(const KParams &p, float r2, ETerms &e)

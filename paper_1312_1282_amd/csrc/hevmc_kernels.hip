@@ -5,10 +5,22 @@
 // coordinates live in LDS for the whole launch (Sec. 3: shared-memory
 // persistence) as structure of arrays x[N], y[N], z[N]; HBM is touched only to
 // load the walker at the start and store it at the end.  Each micro-update's
-// O(N) pair loop of Eq. (7) is spread over the workgroup's lanes (atom
-// i = tid + j*NT), reduced per wave by an xor butterfly and across waves
+// O(N) pair loop of Eq. (7) is spread over the workgroup's lanes (lane tid owns
+// atoms i = tid + j*NT), reduced per wave by an xor butterfly and across waves
 // through a small double-buffered LDS array, so one barrier per micro-update
 // suffices.  Every lane then takes the same Metropolis decision (Eq. (5)).
+//
+// Two variants of the micro-update:
+//  * plain: the pair loop forms u and V at the old and the new position of the
+//    moved atom for every trial move, as Eq. (7) is written;
+//  * row sums (ROWS): each atom's row R_i = sum_{j != i} u(r_ij) is kept in LDS
+//    (FP64), so the forward half of a micro-update evaluates u only at the new
+//    position and dU = sum_i u(|r_s' - r_i|) - R_s.  Only an accepted move needs
+//    the old-position terms: it updates the rows of all atoms and forms dV
+//    (the potential change enters no result for a rejected move).  dV's
+//    workgroup sum rides on the next micro-update's reduction.  The rows are
+//    refreshed exactly by every local-energy pass, can be kept in HBM between
+//    launches, and are checked against u_run (sum_i R_i = 2 U) on load.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,12 +64,14 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *buf)
     __syncthreads();
 }
 
-// Local energy of the walker in LDS (Sec. 2 local value of H; estimators as in
-// oracle): out = (E_L, V, T_PB, T_JF, T_F, U).  Each lane owns atoms
-// i = tid + j*NT and sums over all j != i (every pair twice, no atomics).
+// Local energy of the walker in LDS (Sec. 2 local value of H): out =
+// (E_L, V, T_PB, T_JF, T_F, U).  Each lane owns atoms i = tid + j*NT and sums
+// over all j != i (every pair twice, no atomics).  If rows is not null, the
+// row sums sum_{j != i} u(r_ij) of the lane's atoms are stored there (LDS or
+// global memory).
 template <typename T, int NT>
-__device__ void local_energy_pass(const KParams &p, const T *sx, const T *sy, const T *sz,
-                                  double *buf, double out[6])
+__device__ void local_energy_pass(const KParams &p, const T *sx, const T *sy, const T *sz, double *buf,
+                                  double out[6], double *rows)
 {
     const int n = p.n;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};   // sum |G_i|^2, sum L_i, sum V_i, sum U_i
@@ -84,6 +98,8 @@ __device__ void local_energy_pass(const KParams &p, const T *sx, const T *sy, co
         acc[1] += li;
         acc[2] += vi;
         acc[3] += ui;
+        if (rows)
+            rows[i] = ui;
     }
     block_sum<NT, 4>(acc, buf);
     const double V = 0.5 * acc[2], U = 0.5 * acc[3];
@@ -94,6 +110,26 @@ __device__ void local_energy_pass(const KParams &p, const T *sx, const T *sy, co
     out[3] = -0.5 * p.kappa * acc[1];
     out[4] = p.kappa * acc[0];
     out[5] = U;
+}
+
+// Row sums rows[i] = sum_{j != i} u(r_ij) of the lane's atoms.
+template <typename T, int NT>
+__device__ void row_pass(const KParams &p, const T *sx, const T *sy, const T *sz, double *rows)
+{
+    const int n = p.n;
+    for (int i = threadIdx.x; i < n; i += NT) {
+        const T xi = sx[i], yi = sy[i], zi = sz[i];
+        double ui = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const T dx = min_image(xi - sx[j], p);
+            const T dy = min_image(yi - sy[j], p);
+            const T dz = min_image(zi - sz[j], p);
+            const T r2 = dx * dx + dy * dy + dz * dz;
+            const T u = pair_u(p, r2);
+            ui += (j == i) ? 0.0 : (double)u;
+        }
+        rows[i] = ui;
+    }
 }
 
 // Lane partial of the Eq. (7) sums for moving atom s from (ox,oy,oz) to
@@ -119,6 +155,13 @@ __device__ __forceinline__ void move_partial(const KParams &p, const T *sx, cons
     }
 }
 
+template <typename T>
+__device__ __forceinline__ T dist2(const KParams &p, T ax, T ay, T az_, T bx, T by, T bz)
+{
+    const T dx = min_image(ax - bx, p), dy = min_image(ay - by, p), dz = min_image(az_ - bz, p);
+    return dx * dx + dy * dy + dz * dz;
+}
+
 // fcc start of walker wid with deterministic jitter (see hevmc_init_walkers).
 template <typename T>
 __device__ void fcc_site(const KParams &p, uint32_t wid, int pidx, int nc, double a, T *x, T *y, T *z)
@@ -138,18 +181,23 @@ __device__ void fcc_site(const KParams &p, uint32_t wid, int pidx, int nc, doubl
 
 // --------------------------------------------------------------------------
 // The sweep kernel (hevmc_sweep).  Grid: one workgroup of NT threads per walker.
-template <typename T, int NT>
+// Dynamic LDS: x, y, z (T) and, for ROWS, the row sums (double) at
+// rows_lds_offset(n, sizeof(T)).  rows_hbm ([W][N] doubles) may be null.
+template <typename T, int NT, bool ROWS>
 __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
-                                              hevmc_walker_acc *__restrict__ accs, uint32_t sweep0,
-                                              int32_t nsw, uint32_t mstart, int32_t m)
+                                              hevmc_walker_acc *__restrict__ accs,
+                                              double *__restrict__ rows_hbm, uint32_t sweep0, int32_t nsw,
+                                              uint32_t mstart, int32_t m)
 {
     constexpr int NW = NT / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[2][NW][2];
+    __shared__ double rsl[2];
     __shared__ double ebuf[NW * 4];
     T *sx = reinterpret_cast<T *>(smem_raw);
     const int n = p.n;
     T *sy = sx + n, *sz = sy + n;
+    double *ru = reinterpret_cast<double *>(smem_raw + rows_lds_offset(n, sizeof(T)));
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int w = blockIdx.x;
     const uint32_t wid = p.wid_base + (uint32_t)w;
@@ -160,10 +208,30 @@ __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
     hevmc_walker_acc a = accs[w];
     double u_run = a.u_run, v_run = a.v_run;
     int64_t n_acc = 0, n_try = 0, n_samp = 0, n_swm = 0;
-    __syncthreads();
+    double *rg = rows_hbm ? rows_hbm + (size_t)w * (size_t)n : nullptr;
+    if constexpr (ROWS) {
+        bool valid = false;
+        if (rg) {
+            double c[2] = {0.0, 0.0};
+            for (int i = tid; i < n; i += NT) {
+                const double r = rg[i];
+                ru[i] = r;
+                c[0] += r;
+                c[1] += fabs(r);
+            }
+            block_sum<NT, 2>(c, ebuf);
+            valid = fabs(0.5 * c[0] - u_run) <= 1e-9 * (0.5 * c[1] + 1.0);
+        }
+        __syncthreads();
+        if (!valid)
+            row_pass<T, NT>(p, sx, sy, sz, ru);
+    } else {
+        __syncthreads();
+    }
 
     int last_s = -1;          // atom accepted in the previous micro-update
     T lx = 0, ly = 0, lz = 0; // its new position (LDS copy not yet visible to all waves)
+    double dv_pend = 0.0;     // ROWS: lane partial of dV of the last accepted move
 
     for (int it = 0; it < nsw; ++it) {
         const uint32_t t = sweep0 + (uint32_t)it;
@@ -188,44 +256,119 @@ __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
                 const T nx = (T)wrap_box((double)ox + dx, p.L);
                 const T ny = (T)wrap_box((double)oy + dy, p.L);
                 const T nz = (T)wrap_box((double)oz + dz, p.L);
-                double du = 0.0, dv = 0.0;
-                move_partial<T, NT>(p, sx, sy, sz, s, ox, oy, oz, nx, ny, nz, du, dv);
-                du = wave_sum(du);
-                dv = wave_sum(dv);
-                if (lane == 0) {
-                    red[k & 1][wave][0] = du;
-                    red[k & 1][wave][1] = dv;
-                }
-                __syncthreads();
-                double DU = 0.0, DV = 0.0;
+                const bool owner = (tid == s % NT);
+                if constexpr (ROWS) {
+                    // forward half: u at the new position only
+                    double su = 0.0;
+                    T un_[kRowsPerLane];
 #pragma unroll
-                for (int q = 0; q < NW; ++q) {
-                    DU += red[k & 1][q][0];
-                    DV += red[k & 1][q][1];
-                }
-                const bool accept = exp(2.0 * DU) > xi;
-                if (measured) {
-                    n_try += 1;
-                    n_acc += accept ? 1 : 0;
-                }
-                if (accept) {
-                    u_run += DU;
-                    v_run += DV;
-                    if (tid == s % NT) {
-                        sx[s] = nx; sy[s] = ny; sz[s] = nz;
+                    for (int jj = 0; jj < kRowsPerLane; ++jj) {
+                        const int i = tid + jj * NT;
+                        T uu = T(0);
+                        if (i < n) {
+                            uu = pair_u(p, dist2(p, nx, ny, nz, sx[i], sy[i], sz[i]));
+                            uu = (i == s) ? T(0) : uu;
+                        }
+                        un_[jj] = uu;
+                        su += (double)uu;
                     }
-                    last_s = s;
-                    lx = nx; ly = ny; lz = nz;
+                    const double w0 = wave_sum(su), w1 = wave_sum(dv_pend);
+                    if (lane == 0) {
+                        red[k & 1][wave][0] = w0;
+                        red[k & 1][wave][1] = w1;
+                    }
+                    if (owner)
+                        rsl[k & 1] = ru[s];
+                    __syncthreads();
+                    double SU = 0.0, DVP = 0.0;
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) {
+                        SU += red[k & 1][q][0];
+                        DVP += red[k & 1][q][1];
+                    }
+                    v_run += DVP;
+                    dv_pend = 0.0;
+                    const double DU = SU - rsl[k & 1];
+                    const bool accept = exp(2.0 * DU) > xi;
+                    if (measured) {
+                        n_try += 1;
+                        n_acc += accept ? 1 : 0;
+                    }
+                    if (accept) {
+                        u_run += DU;
+                        // old-position terms: update the rows, form dV
+                        double dvl = 0.0;
+#pragma unroll
+                        for (int jj = 0; jj < kRowsPerLane; ++jj) {
+                            const int i = tid + jj * NT;
+                            if (i < n) {
+                                const T xi_ = sx[i], yi_ = sy[i], zi_ = sz[i];
+                                T uo, vo;
+                                pair_uv(p, dist2(p, ox, oy, oz, xi_, yi_, zi_), uo, vo);
+                                const T vn = pair_v(p, dist2(p, nx, ny, nz, xi_, yi_, zi_));
+                                const bool other = (i != s);
+                                const double dr = other ? (double)un_[jj] - (double)uo : 0.0;
+                                ru[i] += dr;
+                                dvl += other ? (double)vn - (double)vo : 0.0;
+                            }
+                        }
+                        dv_pend = dvl;
+                        if (owner) {
+                            sx[s] = nx; sy[s] = ny; sz[s] = nz;
+                            ru[s] = SU;
+                        }
+                        last_s = s;
+                        lx = nx; ly = ny; lz = nz;
+                    } else {
+                        last_s = -1;
+                    }
                 } else {
-                    last_s = -1;
+                    double du = 0.0, dv = 0.0;
+                    move_partial<T, NT>(p, sx, sy, sz, s, ox, oy, oz, nx, ny, nz, du, dv);
+                    du = wave_sum(du);
+                    dv = wave_sum(dv);
+                    if (lane == 0) {
+                        red[k & 1][wave][0] = du;
+                        red[k & 1][wave][1] = dv;
+                    }
+                    __syncthreads();
+                    double DU = 0.0, DV = 0.0;
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) {
+                        DU += red[k & 1][q][0];
+                        DV += red[k & 1][q][1];
+                    }
+                    const bool accept = exp(2.0 * DU) > xi;
+                    if (measured) {
+                        n_try += 1;
+                        n_acc += accept ? 1 : 0;
+                    }
+                    if (accept) {
+                        u_run += DU;
+                        v_run += DV;
+                        if (owner) {
+                            sx[s] = nx; sy[s] = ny; sz[s] = nz;
+                        }
+                        last_s = s;
+                        lx = nx; ly = ny; lz = nz;
+                    } else {
+                        last_s = -1;
+                    }
                 }
             }
+        }
+        if constexpr (ROWS) {
+            // the last accepted move's dV has not been reduced yet
+            double f[1] = {dv_pend};
+            block_sum<NT, 1>(f, ebuf);
+            v_run += f[0];
+            dv_pend = 0.0;
         }
         if (measured) {
             if (m > 0 && (t - mstart + 1) % (uint32_t)m == 0) {
                 __syncthreads();
                 double el[6];
-                local_energy_pass<T, NT>(p, sx, sy, sz, ebuf, el);
+                local_energy_pass<T, NT>(p, sx, sy, sz, ebuf, el, ROWS ? ru : nullptr);
                 if (tid == 0) {
                     nsum(a.sum_e, a.c_e, el[0]);
                     nsum(a.sum_e2, a.c_e2, el[0] * el[0]);
@@ -247,6 +390,11 @@ __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
     __syncthreads();
     for (int i = tid; i < 3 * n; i += NT)
         g[i] = sx[i];
+    if constexpr (ROWS) {
+        if (rg)
+            for (int i = tid; i < n; i += NT)
+                rg[i] = ru[i];
+    }
     if (tid == 0) {
         a.u_run = u_run;
         a.v_run = v_run;
@@ -273,18 +421,18 @@ __global__ __launch_bounds__(NT) void k_local_energy(KParams p, const T *__restr
         sx[i] = g[i];
     __syncthreads();
     double el[6];
-    local_energy_pass<T, NT>(p, sx, sx + n, sx + 2 * n, ebuf, el);
+    local_energy_pass<T, NT>(p, sx, sx + n, sx + 2 * n, ebuf, el, nullptr);
     if (threadIdx.x == 0)
         for (int q = 0; q < 6; ++q)
             out[(size_t)blockIdx.x * 6 + q] = el[q];
 }
 
 // Start walkers (hevmc_init_walkers): optional fcc start, then running totals
-// from a full evaluation and zeroed accumulators.
+// (and row sums, if rows is not null) from a full evaluation, zeroed accumulators.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_init(KParams p, T *__restrict__ coords,
-                                             hevmc_walker_acc *__restrict__ accs, int fcc, int nc,
-                                             double a_lat)
+                                             hevmc_walker_acc *__restrict__ accs, double *__restrict__ rows,
+                                             int fcc, int nc, double a_lat)
 {
     constexpr int NW = NT / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -306,7 +454,8 @@ __global__ __launch_bounds__(NT) void k_init(KParams p, T *__restrict__ coords,
     }
     __syncthreads();
     double el[6];
-    local_energy_pass<T, NT>(p, sx, sx + n, sx + 2 * n, ebuf, el);
+    local_energy_pass<T, NT>(p, sx, sx + n, sx + 2 * n, ebuf, el,
+                             rows ? rows + (size_t)blockIdx.x * (size_t)n : nullptr);
     if (threadIdx.x == 0) {
         hevmc_walker_acc a = {};
         a.u_run = el[5];
@@ -346,7 +495,7 @@ __global__ __launch_bounds__(NT) void k_move_delta(KParams p, const T *__restric
     const T nz = (T)wrap_box((double)oz + delta[3 * w + 2], p.L);
     double v[2] = {0.0, 0.0};
     move_partial<T, NT>(p, sx, sx + n, sx + 2 * n, s, ox, oy, oz, nx, ny, nz, v[0], v[1]);
-    // same reduction order as the sweep: wave butterfly, then waves in order
+    // same reduction order as the plain sweep: wave butterfly, then waves in order
     block_sum<NT, 2>(v, ebuf);
     if (threadIdx.x == 0) {
         out[2 * w + 0] = v[0];
@@ -373,19 +522,33 @@ __global__ void k_draw_moves(KParams p, uint32_t t, int32_t *__restrict__ s_out,
 }
 
 // --------------------------------------------------------------------------
-// Launchers.  Each checks nothing itself: the C ABI validated the arguments.
+// Launchers.  The C ABI validated the arguments and planned the launch.
+
+template <typename K>
+static hipError_t allow_lds(K kern, size_t bytes)
+{
+    return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
 
 template <typename T, int NT>
-static hipError_t launch_sweep_t(const Launch &L, void *coords, hevmc_walker_acc *acc, uint32_t sweep0,
-                                 int32_t nsw, uint32_t mstart, int32_t m)
+static hipError_t launch_sweep_t(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows,
+                                 uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t m)
 {
-    auto kern = k_sweep<T, NT>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)L.lds_bytes);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k,
-                       (T *)coords, acc, sweep0, nsw, mstart, m);
+    if (L.rows) {
+        auto kern = k_sweep<T, NT, true>;
+        hipError_t e = allow_lds(kern, L.lds_bytes);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k, (T *)coords,
+                           acc, rows, sweep0, nsw, mstart, m);
+    } else {
+        auto kern = k_sweep<T, NT, false>;
+        hipError_t e = allow_lds(kern, L.lds_bytes);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k, (T *)coords,
+                           acc, (double *)nullptr, sweep0, nsw, mstart, m);
+    }
     return hipGetLastError();
 }
 
@@ -393,8 +556,7 @@ template <typename T, int NT>
 static hipError_t launch_energy_t(const Launch &L, const void *coords, double *out)
 {
     auto kern = k_local_energy<T, NT>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)L.lds_bytes);
+    hipError_t e = allow_lds(kern, L.lds_bytes);
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k,
@@ -403,16 +565,15 @@ static hipError_t launch_energy_t(const Launch &L, const void *coords, double *o
 }
 
 template <typename T, int NT>
-static hipError_t launch_init_t(const Launch &L, void *coords, hevmc_walker_acc *acc, int fcc, int nc,
-                                double a_lat)
+static hipError_t launch_init_t(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows, int fcc,
+                                int nc, double a_lat)
 {
     auto kern = k_init<T, NT>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)L.lds_bytes);
+    hipError_t e = allow_lds(kern, L.lds_bytes);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k,
-                       (T *)coords, acc, fcc, nc, a_lat);
+    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k, (T *)coords, acc,
+                       rows, fcc, nc, a_lat);
     return hipGetLastError();
 }
 
@@ -421,8 +582,7 @@ static hipError_t launch_delta_t(const Launch &L, const void *coords, const int3
                                  double *out)
 {
     auto kern = k_move_delta<T, NT>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)L.lds_bytes);
+    hipError_t e = allow_lds(kern, L.lds_bytes);
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k,
@@ -451,10 +611,10 @@ static hipError_t launch_delta_t(const Launch &L, const void *coords, const int3
         return hipErrorInvalidValue;                                                   \
     } while (0)
 
-hipError_t launch_sweep(const Launch &L, void *coords, hevmc_walker_acc *acc, uint32_t sweep0, int32_t nsw,
-                        uint32_t mstart, int32_t m)
+hipError_t launch_sweep(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows, uint32_t sweep0,
+                        int32_t nsw, uint32_t mstart, int32_t m)
 {
-    HEVMC_DISPATCH(launch_sweep_t, coords, acc, sweep0, nsw, mstart, m);
+    HEVMC_DISPATCH(launch_sweep_t, coords, acc, rows, sweep0, nsw, mstart, m);
 }
 
 hipError_t launch_local_energy(const Launch &L, const void *coords, double *out)
@@ -462,9 +622,10 @@ hipError_t launch_local_energy(const Launch &L, const void *coords, double *out)
     HEVMC_DISPATCH(launch_energy_t, coords, out);
 }
 
-hipError_t launch_init(const Launch &L, void *coords, hevmc_walker_acc *acc, int fcc, int nc, double a_lat)
+hipError_t launch_init(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows, int fcc, int nc,
+                       double a_lat)
 {
-    HEVMC_DISPATCH(launch_init_t, coords, acc, fcc, nc, a_lat);
+    HEVMC_DISPATCH(launch_init_t, coords, acc, rows, fcc, nc, a_lat);
 }
 
 hipError_t launch_move_delta(const Launch &L, const void *coords, const int32_t *s, const double *d,

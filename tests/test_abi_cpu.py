@@ -28,14 +28,14 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_parameter_struct_layouts():
-    assert C.sizeof(abi.Params) == 64
+    assert C.sizeof(abi.Params) == 72
     assert C.sizeof(abi.WalkerAcc) == 160
 
 
 @pytest.mark.parametrize("bad", [
     dict(n=1), dict(n_walkers=0), dict(precision=7), dict(order=3), dict(density=0.0),
     dict(density=float("nan")), dict(b=-1.0), dict(hbar2_over_m=0.0), dict(step_sigma=0.0),
-    dict(threads=96),
+    dict(threads=96), dict(variant=3),
 ])
 def test_invalid_parameters_rejected(bad):
     kw = dict(n=108, n_walkers=4)

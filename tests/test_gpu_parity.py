@@ -35,9 +35,10 @@ def osys(n, rho=RHO, b=B, step=STEP, seed=1, fp32=False, order=0):
                     seed=seed, order=order)
 
 
-def gparams(n, W, precision=abi.FP64, threads=0, seed=1, wbase=0, order=0, b=B, rho=RHO, step=STEP):
+def gparams(n, W, precision=abi.FP64, threads=0, seed=1, wbase=0, order=0, b=B, rho=RHO, step=STEP,
+            variant=abi.VARIANT_AUTO):
     return abi.make_params(n, W, precision=precision, density=rho, b=b, step_sigma=step, seed=seed,
-                           walker_id_base=wbase, threads=threads, order=order)
+                           walker_id_base=wbase, threads=threads, order=order, variant=variant)
 
 
 def within(got, ref, scale, rel):
@@ -164,12 +165,19 @@ def test_fcc_start_and_initial_totals(n, precision):
 # ---------------------------------------------------------------------------
 # chains in lockstep
 
-def _gpu_chain(p, splits, measure_start, m):
+def _gpu_chain(p, splits, measure_start, m, keep_rows=True, rows_fill=None):
+    """Run the GPU chain from the fcc start in launches of the given lengths.
+    keep_rows: keep the row sums in a device buffer between launches (else the
+    kernel recomputes them at each launch); rows_fill: overwrite that buffer
+    with this value after initialisation (a stale buffer)."""
     coords, acc = abi.alloc_state(p)
-    abi.init_walkers(p, coords, acc, fcc_start=True)
+    rows = abi.alloc_rows(p) if keep_rows else None
+    abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
+    if rows is not None and rows_fill is not None:
+        rows.fill_(rows_fill)
     t = 0
     for k in splits:
-        abi.sweep(p, coords, acc, t, k, measure_start, m)
+        abi.sweep(p, coords, acc, t, k, measure_start, m, rows=rows)
         t += k
     torch.cuda.synchronize()
     return coords.cpu().numpy(), abi.acc_to_numpy(acc)
@@ -195,23 +203,42 @@ def _compare_walker(xg, ag, xo, ao):
     assert ag["v_run"] == pytest.approx(ao.v_run, rel=1e-10, abs=1e-9)
 
 
-def test_lockstep_chain_n108_full_run():
+VARIANTS = [abi.VARIANT_PLAIN, abi.VARIANT_ROWS]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("keep_rows", [True, False])
+def test_lockstep_chain_n108_full_run(variant, keep_rows):
     """N=108, one walker, 200 equilibration + 1000 measured sweeps, local energy
     every sweep, split over launches of different lengths."""
     wl = configs.C1_SMALL_FP64
-    p = abi.params_for(wl)
+    p = abi.params_for(wl, variant=variant)
     total = wl.equil + wl.measured
-    xg, ag = _gpu_chain(p, [150, 50, 400, 600], wl.equil, wl.m)
+    xg, ag = _gpu_chain(p, [150, 50, 400, 600], wl.equil, wl.m, keep_rows=keep_rows)
     s_ = osys(wl.n, seed=wl.seed)
     xo, ao = _oracle_chain(s_, 0, total, wl.equil, wl.m)
     _compare_walker(xg[0], ag[0], xo, ao)
     assert ao.n_samples == 1000
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_lockstep_without_energy_refresh(variant):
+    """Sweeps with no local-energy pass: the running totals (and, for the row
+    variant, the rows) are only updated incrementally for 60 sweeps."""
+    n, W = 256, 2
+    p = gparams(n, W, seed=21, variant=variant)
+    xg, ag = _gpu_chain(p, [25, 35], 0, 0)
+    s_ = osys(n, seed=21)
+    for w in range(W):
+        xo, ao = _oracle_chain(s_, w, 60, 0, 0)
+        _compare_walker(xg[w], ag[w], xo, ao)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("threads", [128, 256])
-def test_lockstep_sequential_order_and_threads(threads):
+def test_lockstep_sequential_order_and_threads(variant, threads):
     n, W = 256, 3
-    p = gparams(n, W, threads=threads, order=1, seed=9, wbase=40)
+    p = gparams(n, W, threads=threads, order=1, seed=9, wbase=40, variant=variant)
     xg, ag = _gpu_chain(p, [7, 5], 4, 2)
     s_ = osys(n, seed=9, order=1)
     for w in range(W):
@@ -219,21 +246,34 @@ def test_lockstep_sequential_order_and_threads(threads):
         _compare_walker(xg[w], ag[w], xo, ao)
 
 
-def test_split_launches_bitwise_identical():
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_split_launches_bitwise_identical(variant):
     n, W = 256, 4
-    p = gparams(n, W, seed=3)
+    p = gparams(n, W, seed=3, variant=variant)
     x1, a1 = _gpu_chain(p, [10], 2, 3)
     x2, a2 = _gpu_chain(p, [3, 4, 3], 2, 3)
     assert np.array_equal(x1, x2)
     assert a1.tobytes() == a2.tobytes()
 
 
-def test_n2048_w512_launch_sampled_walkers():
+def test_stale_rows_buffer_is_recomputed():
+    """A rows buffer that disagrees with u_run is detected and rebuilt: the
+    result equals a run that recomputes the rows at every launch."""
+    n, W = 256, 2
+    p = gparams(n, W, seed=5, variant=abi.VARIANT_ROWS)
+    x1, a1 = _gpu_chain(p, [6], 0, 3, keep_rows=False)
+    x2, a2 = _gpu_chain(p, [6], 0, 3, keep_rows=True, rows_fill=0.25)
+    assert np.array_equal(x1, x2)
+    assert a1.tobytes() == a2.tobytes()
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_n2048_w512_launch_sampled_walkers(variant):
     """The benchmark's launch: N=2048, 512 walkers, FP64, five sweeps with a
     local-energy sample after the fifth; walkers 0, 255 and 511 are replayed by
     the oracle."""
     wl = configs.C2_N2048_FP64
-    p = abi.params_for(wl)
+    p = abi.params_for(wl, variant=variant)
     xg, ag = _gpu_chain(p, [5], 0, 5)
     s_ = osys(wl.n, seed=wl.seed)
     picks = [0, 255, 511]
