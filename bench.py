@@ -51,7 +51,24 @@ def parse():
     ap.add_argument("--variant", type=int, default=0, help="sweep variant: 0 auto, 1 plain, 2 row sums")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=5)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="instead of the workload, run 5 plain device copies of MIB MiB (the reference "
+                         "kernel for scaling HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    """Plain device-to-device copies of a known size: FETCH_SIZE and WRITE_SIZE
+    of these dispatches are what the counters read for mib MiB each way."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_mib": mib, "bytes_each_way": n * 8}), flush=True)
 
 
 def cpu_baseline(wl, sweeps):
@@ -96,6 +113,9 @@ def main():
 
     from paper_1312_1282_amd import abi, configs
 
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     wl = configs.ALL[args.workload]
     p = abi.params_for(wl, threads=args.threads, variant=args.variant)
     dtype = "f32" if wl.precision == configs.FP32 else "f64"

@@ -102,16 +102,25 @@ hevmc_status check_params(const hevmc_params *p)
 }
 
 // Threads per walker when the caller leaves the choice to the library: about
-// 8 atoms per lane, at least 2 waves, at most 16.
+// 8 atoms per lane, 2 to 8 waves.
 int default_threads(int n)
 {
     if (n <= 1024)
         return 128;
     if (n <= 3072)
         return 256;
-    if (n <= 6144)
-        return 512;
-    return 1024;
+    return 512;
+}
+
+// Waves one SIMD can hold for a kernel using vgprs registers per thread
+// (512 registers per lane per SIMD, allocated in granules of 8; at most 8 waves).
+int waves_per_simd(int vgprs)
+{
+    if (vgprs <= 0)
+        return 8;
+    const int alloc = (vgprs + 7) & ~7;
+    const int w = 512 / alloc;
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
 size_t lds_needed(const hevmc_params *p)
@@ -152,11 +161,16 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L)
     const bool use_rows = p->variant == HEVMC_VARIANT_ROWS || (p->variant == HEVMC_VARIANT_AUTO && rows_ok);
     const size_t need = use_rows ? need_rows : need_plain;
     size_t lds = need;
+    // walkers a compute unit can hold: by LDS, and by waves (4 SIMDs, register
+    // file shared by the waves of a SIMD)
+    const int waves_per_walker = threads / 64;
+    const int by_waves = 4 * waves_per_simd(sweep_vgprs(p->precision == HEVMC_FP32, threads, use_rows)) /
+                         waves_per_walker;
     const int per_cu = (p->n_walkers + d.cus - 1) / d.cus;
     for (int r = per_cu; r >= 1; --r) {
         if (per_cu % r != 0)
             continue;
-        if ((size_t)r * (need + stat) > d.lds_per_cu)
+        if ((size_t)r * (need + stat) > d.lds_per_cu || (r > by_waves && r > 1))
             continue;
         size_t even = d.lds_per_cu / (size_t)r;
         even = even > stat + 128 ? even - stat - 128 : 0;

@@ -93,11 +93,14 @@ __device__ __forceinline__ void draw_move(const KParams &p, uint32_t k, uint32_t
     dz = p.step * (R2 * cos(two_pi * unit32(b[2])));
 }
 
-// Periodic wrap of a moved coordinate into [0, L) (Sec. 5.1).
-__device__ __forceinline__ double wrap_box(double y, double L)
+// Periodic wrap of a moved coordinate into [0, L) (Sec. 5.1): y - L floor(y/L),
+// with y/L formed as y * (1/L) and the two results rounding can leave outside
+// [0, L) moved back in.
+__device__ __forceinline__ double wrap_box(double y, double L, double invL)
 {
-    double x = y - L * floor(y / L);
-    return (x >= L) ? x - L : x;
+    double x = y - L * floor(y * invL);
+    x = (x >= L) ? x - L : x;
+    return (x < 0.0) ? x + L : x;
 }
 
 // Minimum image of one coordinate difference (Sec. 5.1).
@@ -189,10 +192,14 @@ __device__ __forceinline__ void pair_uv(const KParams &p, double r2, double &u, 
     v = in ? vv : 0.0;
 }
 
-// FP64: u(r) alone (the forward half of a micro-update needs only ln psi).
-__device__ __forceinline__ double pair_u(const KParams &p, double r2)
+// Reciprocal distance from r^2 in the pair's precision.
+__device__ __forceinline__ double inv_sqrt(double r2) { return rsq_nr(r2); }
+__device__ __forceinline__ float inv_sqrt(float r2) { return __builtin_amdgcn_rsqf(r2); }
+
+// FP64: u(r) alone, given r^2 and 1/r (the forward half of a micro-update
+// needs only ln psi).
+__device__ __forceinline__ double pair_u_ri(const KParams &p, double r2, double ri)
 {
-    const double ri = rsq_nr(r2);
     const double r = r2 * ri;
     const double rpi = rcp_nr(p.L - r);
     const double ri2 = ri * ri, rpi2 = rpi * rpi;
@@ -200,10 +207,9 @@ __device__ __forceinline__ double pair_u(const KParams &p, double r2)
     return r2 <= p.h2 ? uu : 0.0;
 }
 
-// FP64: V(r) alone.
-__device__ __forceinline__ double pair_v(const KParams &p, double r2)
+// FP64: V(r) alone, given r^2 and 1/r.
+__device__ __forceinline__ double pair_v_ri(const KParams &p, double r2, double ri)
 {
-    const double ri = rsq_nr(r2);
     const double r = r2 * ri;
     const double rep = az::A * exp_neg(fma(az::beta_rm2, r2, -(az::alpha_rm * r)));
     const double y = az::rm2 * (ri * ri);
@@ -244,9 +250,8 @@ __device__ __forceinline__ void pair_uv(const KParams &p, float r2, float &u, fl
     v = in ? vv : 0.0f;
 }
 
-__device__ __forceinline__ float pair_u(const KParams &p, float r2)
+__device__ __forceinline__ float pair_u_ri(const KParams &p, float r2, float ri)
 {
-    const float ri = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * ri;
     const float rpi = __builtin_amdgcn_rcpf(p.Lf - r);
     const float ri2 = ri * ri, rpi2 = rpi * rpi;
@@ -254,9 +259,8 @@ __device__ __forceinline__ float pair_u(const KParams &p, float r2)
     return r2 <= p.h2f ? uu : 0.0f;
 }
 
-__device__ __forceinline__ float pair_v(const KParams &p, float r2)
+__device__ __forceinline__ float pair_v_ri(const KParams &p, float r2, float ri)
 {
-    const float ri = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * ri;
     const float x = r * (float)az::inv_rm;
     const float rep = (float)az::A * fexp(x * ((float)az::beta * x - (float)az::alpha));
@@ -336,16 +340,43 @@ __device__ __forceinline__ void pair_energy(const KParams &p, float r2, ETerms &
     e.lap = in ? (double)(d2u + 2.0f * dur) : 0.0;
 }
 
+// Metropolis decision of Eq. (5): accept if |psi'|^2/|psi|^2 = exp(2 dU) > xi,
+// xi in (0, 1); for dU >= 0 the ratio is >= 1 > xi.
+__device__ __forceinline__ bool metropolis_accept(double du, double xi)
+{
+    return du >= 0.0 || exp_neg(2.0 * du) > xi;
+}
+
 // --------------------------------------------------------------------------
-// Reductions.  The xor butterfly leaves the bitwise-identical total in every
-// lane (each step adds the same two operands in both partner lanes), so the
-// result depends only on the data and the workgroup shape.
+// Reductions.  Within each 16-lane row, four DPP steps (swap neighbours, swap
+// pairs, mirror halves, mirror the row) add each lane's value to a partner's,
+// so every lane of the row ends with the bitwise-identical row sum (both
+// partners add the same two operands).  The four row sums are then read as
+// scalars and added in a fixed order.  The total depends only on the data and
+// the lane layout, and every lane holds the same value.  All 64 lanes must be
+// active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1)
-        v += __shfl_xor(v, m, 64);
-    return v;
+    v += dpp_double<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_double<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_double<0x141>(v);   // row_half_mirror
+    v += dpp_double<0x140>(v);   // row_mirror
+    return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
 }
 
 // Neumaier-compensated accumulation: value = s + c.

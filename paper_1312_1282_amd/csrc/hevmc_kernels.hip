@@ -6,9 +6,9 @@
 // persistence) as structure of arrays x[N], y[N], z[N]; HBM is touched only to
 // load the walker at the start and store it at the end.  Each micro-update's
 // O(N) pair loop of Eq. (7) is spread over the workgroup's lanes (lane tid owns
-// atoms i = tid + j*NT), reduced per wave by an xor butterfly and across waves
-// through a small double-buffered LDS array, so one barrier per micro-update
-// suffices.  Every lane then takes the same Metropolis decision (Eq. (5)).
+// atoms i = tid + j*NT), reduced per wave with DPP row sums and lane reads and
+// across waves through a small double-buffered LDS array, so one barrier per
+// micro-update suffices.  Every lane then takes the same Metropolis decision (Eq. (5)).
 //
 // Two variants of the micro-update:
 //  * plain: the pair loop forms u and V at the old and the new position of the
@@ -31,12 +31,6 @@
 namespace hevmc {
 
 __device__ __forceinline__ int readlane_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
-__device__ __forceinline__ double readlane_d(double v, int lane)
-{
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-    return __hiloint2double(hi, lo);
-}
 
 // Sum of NV doubles over the workgroup; every thread gets the same totals.
 // buf must hold NW*NV doubles; it is free again when the function returns.
@@ -125,7 +119,7 @@ __device__ void row_pass(const KParams &p, const T *sx, const T *sy, const T *sz
             const T dy = min_image(yi - sy[j], p);
             const T dz = min_image(zi - sz[j], p);
             const T r2 = dx * dx + dy * dy + dz * dz;
-            const T u = pair_u(p, r2);
+            const T u = pair_u_ri(p, r2, inv_sqrt(r2));
             ui += (j == i) ? 0.0 : (double)u;
         }
         rows[i] = ui;
@@ -245,34 +239,40 @@ __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
             for (int j = 0; j < kend; ++j) {
                 const int k = k0 + j;
                 const int s = readlane_i(bs, j);
-                const double xi = readlane_d(bxi, j);
-                const double dx = readlane_d(bdx, j), dy = readlane_d(bdy, j), dz = readlane_d(bdz, j);
+                const double xi = lane_value(bxi, j);
+                const double dx = lane_value(bdx, j), dy = lane_value(bdy, j), dz = lane_value(bdz, j);
                 T ox, oy, oz;
                 if (s == last_s) {
                     ox = lx; oy = ly; oz = lz;
                 } else {
                     ox = sx[s]; oy = sy[s]; oz = sz[s];
                 }
-                const T nx = (T)wrap_box((double)ox + dx, p.L);
-                const T ny = (T)wrap_box((double)oy + dy, p.L);
-                const T nz = (T)wrap_box((double)oz + dz, p.L);
+                const T nx = (T)wrap_box((double)ox + dx, p.L, p.invL);
+                const T ny = (T)wrap_box((double)oy + dy, p.L, p.invL);
+                const T nz = (T)wrap_box((double)oz + dz, p.L, p.invL);
                 const bool owner = (tid == s % NT);
                 if constexpr (ROWS) {
-                    // forward half: u at the new position only
+                    // forward half: u at the new position only; r^2 and 1/r are
+                    // kept for the potential if the move is accepted
                     double su = 0.0;
-                    T un_[kRowsPerLane];
+                    T un_[kRowsPerLane], r2n_[kRowsPerLane], rin_[kRowsPerLane];
 #pragma unroll
                     for (int jj = 0; jj < kRowsPerLane; ++jj) {
                         const int i = tid + jj * NT;
-                        T uu = T(0);
+                        T uu = T(0), r2 = T(1), ri = T(1);
                         if (i < n) {
-                            uu = pair_u(p, dist2(p, nx, ny, nz, sx[i], sy[i], sz[i]));
+                            r2 = dist2(p, nx, ny, nz, sx[i], sy[i], sz[i]);
+                            ri = inv_sqrt(r2);
+                            uu = pair_u_ri(p, r2, ri);
                             uu = (i == s) ? T(0) : uu;
                         }
                         un_[jj] = uu;
+                        r2n_[jj] = r2;
+                        rin_[jj] = ri;
                         su += (double)uu;
                     }
-                    const double w0 = wave_sum(su), w1 = wave_sum(dv_pend);
+                    const double w0 = wave_sum(su);
+                    const double w1 = (last_s >= 0) ? wave_sum(dv_pend) : 0.0;
                     if (lane == 0) {
                         red[k & 1][wave][0] = w0;
                         red[k & 1][wave][1] = w1;
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
                     v_run += DVP;
                     dv_pend = 0.0;
                     const double DU = SU - rsl[k & 1];
-                    const bool accept = exp(2.0 * DU) > xi;
+                    const bool accept = metropolis_accept(DU, xi);
                     if (measured) {
                         n_try += 1;
                         n_acc += accept ? 1 : 0;
@@ -302,10 +302,11 @@ __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
                         for (int jj = 0; jj < kRowsPerLane; ++jj) {
                             const int i = tid + jj * NT;
                             if (i < n) {
-                                const T xi_ = sx[i], yi_ = sy[i], zi_ = sz[i];
-                                T uo, vo;
-                                pair_uv(p, dist2(p, ox, oy, oz, xi_, yi_, zi_), uo, vo);
-                                const T vn = pair_v(p, dist2(p, nx, ny, nz, xi_, yi_, zi_));
+                                const T r2o = dist2(p, ox, oy, oz, sx[i], sy[i], sz[i]);
+                                const T rio = inv_sqrt(r2o);
+                                const T uo = pair_u_ri(p, r2o, rio);
+                                const T vo = pair_v_ri(p, r2o, rio);
+                                const T vn = pair_v_ri(p, r2n_[jj], rin_[jj]);
                                 const bool other = (i != s);
                                 const double dr = other ? (double)un_[jj] - (double)uo : 0.0;
                                 ru[i] += dr;
@@ -338,7 +339,7 @@ __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
                         DU += red[k & 1][q][0];
                         DV += red[k & 1][q][1];
                     }
-                    const bool accept = exp(2.0 * DU) > xi;
+                    const bool accept = metropolis_accept(DU, xi);
                     if (measured) {
                         n_try += 1;
                         n_acc += accept ? 1 : 0;
@@ -490,9 +491,9 @@ __global__ __launch_bounds__(NT) void k_move_delta(KParams p, const T *__restric
         return;
     }
     const T ox = sx[s], oy = sx[n + s], oz = sx[2 * n + s];
-    const T nx = (T)wrap_box((double)ox + delta[3 * w + 0], p.L);
-    const T ny = (T)wrap_box((double)oy + delta[3 * w + 1], p.L);
-    const T nz = (T)wrap_box((double)oz + delta[3 * w + 2], p.L);
+    const T nx = (T)wrap_box((double)ox + delta[3 * w + 0], p.L, p.invL);
+    const T ny = (T)wrap_box((double)oy + delta[3 * w + 1], p.L, p.invL);
+    const T nz = (T)wrap_box((double)oz + delta[3 * w + 2], p.L, p.invL);
     double v[2] = {0.0, 0.0};
     move_partial<T, NT>(p, sx, sx + n, sx + 2 * n, s, ox, oy, oz, nx, ny, nz, v[0], v[1]);
     // same reduction order as the plain sweep: wave butterfly, then waves in order
@@ -610,6 +611,29 @@ static hipError_t launch_delta_t(const Launch &L, const void *coords, const int3
         }                                                                              \
         return hipErrorInvalidValue;                                                   \
     } while (0)
+
+template <typename T, int NT>
+static const void *sweep_fn(bool rows)
+{
+    return rows ? (const void *)k_sweep<T, NT, true> : (const void *)k_sweep<T, NT, false>;
+}
+
+// Registers per thread of the sweep kernel a launch would use (0 if unknown).
+int sweep_vgprs(bool fp32, int threads, bool rows)
+{
+    const void *f = nullptr;
+    switch (threads) {
+    case 128: f = fp32 ? sweep_fn<float, 128>(rows) : sweep_fn<double, 128>(rows); break;
+    case 256: f = fp32 ? sweep_fn<float, 256>(rows) : sweep_fn<double, 256>(rows); break;
+    case 512: f = fp32 ? sweep_fn<float, 512>(rows) : sweep_fn<double, 512>(rows); break;
+    case 1024: f = fp32 ? sweep_fn<float, 1024>(rows) : sweep_fn<double, 1024>(rows); break;
+    default: return 0;
+    }
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, f) != hipSuccess)
+        return 0;
+    return a.numRegs;
+}
 
 hipError_t launch_sweep(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows, uint32_t sweep0,
                         int32_t nsw, uint32_t mstart, int32_t m)
