@@ -5,8 +5,8 @@ density 0.02186 / A^3, b = 1.15 sigma, 512 walkers, FP64, Gaussian moves with
 ~50% acceptance, local energy every 5 sweeps.  One step = one launch of the
 sweep kernel: 5 sweeps of every walker (N micro-updates each, the O(N) pair loop
 per micro-update) followed by one O(N^2) local-energy evaluation per walker.
-Warm-up steps double as equilibration; measurement starts with the first timed
-step.
+Warm-up steps (the same launches) double as equilibration; accumulators restart
+with the first timed step.
 
 Prints one JSON line: moves/s, the roofline of the sweep kernel (vector ALU,
 FP64) from per-launch HIP events, and the CPU oracle timed on the host cores on
@@ -55,6 +55,29 @@ def parse():
                     help="instead of the workload, run 5 plain device copies of MIB MiB (the reference "
                          "kernel for scaling HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def measured_traffic(workload):
+    """HBM bytes per sweep launch from the calibrated FETCH_SIZE + WRITE_SIZE
+    counters recorded in profiles/traffic.txt, if they were taken on the
+    kernel sources as they are now; else None."""
+    import glob
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1312_1282_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    digest = h.hexdigest()
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 3 and not line.startswith("#") and parts[0] == workload and parts[1] == digest:
+                return int(parts[2])
+    return None
 
 
 def calibrate_copy(mib):
@@ -126,11 +149,14 @@ def main():
     S = args.sweeps_per_step
     m = wl.m
     t = 0
+    # warm-up launches are the same work as timed ones (equilibration with
+    # local energies); the accumulators are then restarted from the current
+    # configurations, so every launch of the sweep kernel costs the same
     for _ in range(args.warmup):
-        abi.sweep(p, coords, acc, t, S, abi.NO_MEASURE, 0, rows=rows)
+        abi.sweep(p, coords, acc, t, S, 0, m, rows=rows)
         t += S
+    abi.init_walkers(p, coords, acc, fcc_start=False, rows=rows)
     torch.cuda.synchronize()
-    # fresh accumulators for the measured part (running totals kept)
     mstart = t
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
@@ -201,7 +227,8 @@ def main():
             "peak": PEAK[dtype],
             "unit": "TFLOP/s",
             "frac": achieved / PEAK[dtype],
-            "traffic": None,
+            "traffic": measured_traffic(wl.name),
+            "traffic_unit": "bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
             "kernel": "k_sweep",
             "launch_ms_avg": float(launch_ms.mean()),
             "flop_per_launch": flop_launch,
