@@ -49,8 +49,16 @@ def parse():
     ap.add_argument("--sweeps-per-step", type=int, default=5)
     ap.add_argument("--threads", type=int, default=0, help="threads per walker (0 = library choice)")
     ap.add_argument("--variant", type=int, default=0, help="sweep variant: 0 auto, 1 plain, 2 row sums")
+    ap.add_argument("--n", type=int, default=0, help="override the workload's atoms per walker")
+    ap.add_argument("--walkers", type=int, default=0, help="override the workload's walker count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=5)
+    ap.add_argument("--serve", type=int, default=0, metavar="REQUESTS",
+                    help="instead of the sweep throughput, serve this many requests of the Poisson request "
+                         "stream (20/s) until each reaches 1 mK/atom and report p50/p99 time-to-1mK")
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-time-limit", type=float, default=None,
+                    help="stop serving after this many seconds; unfinished requests are reported as censored")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the workload, run 5 plain device copies of MIB MiB (the reference "
                          "kernel for scaling HBM byte counters) and exit")
@@ -78,6 +86,52 @@ def measured_traffic(workload):
             if len(parts) == 3 and not line.startswith("#") and parts[0] == workload and parts[1] == digest:
                 return int(parts[2])
     return None
+
+
+def serve(args):
+    """Served time-to-1 mK/atom for the first `args.serve` requests of the
+    seeded request stream, arriving in real time."""
+    import numpy as np
+    import torch
+
+    from paper_1312_1282_amd import serving
+
+    torch.cuda.set_device(0)
+    reqs = serving.request_stream(args.serve, rate=args.serve_rate)
+    server = serving.Server()
+    t0 = time.perf_counter()
+    server.run(reqs, realtime=True, time_limit=args.serve_time_limit,
+               log=lambda m: print(m, file=sys.stderr, flush=True))
+    wall = time.perf_counter() - t0
+    lat = serving.latency_summary(reqs, server.censored_at)
+    done = [r for r in reqs if r.done is not None]
+    moves = sum(r.walkers * r.n * r.sweeps for r in done)
+    busy_span = max(r.done for r in done) - min(r.admitted for r in done) if done else float("nan")
+    line = {
+        "metric": "single-particle Metropolis moves/s at N=2048; served p50/p99 time-to-1mK",
+        "value": lat.get("p99_s"),
+        "unit": "s (p99 time-to-1mK)",
+        "higher_is_better": False,
+        "n_gpus": 1,
+        "dtype": "mixed f32/f64",
+        "data": "synthetic: seeded Poisson stream of liquid 4He VMC requests",
+        "config": {"workload": "he4_serving_stream", "requests": args.serve, "arrival_rate_per_s": args.serve_rate,
+                   "target_se_K": server.target_se, "equil_sweeps": server.equil, "energy_every": server.m,
+                   "check_every": server.check_every, "quantum_sweeps": server.quantum},
+        "serving": {
+            **lat,
+            "offered_rate_per_s": args.serve_rate,
+            "completed_per_s": len(done) / busy_span if done else 0.0,
+            "moves_per_s": moves / busy_span if done else 0.0,
+            "wall_s": wall,
+            "launches": server.launches,
+            "rejected": [r.rid for r in reqs if r.rejected],
+            "requests": [{"rid": r.rid, "n": r.n, "walkers": r.walkers, "precision": r.precision,
+                          "arrival_s": round(r.arrival, 4), "admitted_s": r.admitted, "done_s": r.done,
+                          "sweeps": r.sweeps, "E_per_atom_K": r.energy, "se_K": r.se} for r in reqs],
+        },
+    }
+    print(json.dumps(line), flush=True)
 
 
 def calibrate_copy(mib):
@@ -139,7 +193,13 @@ def main():
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
         return
+    if args.serve:
+        serve(args)
+        return
     wl = configs.ALL[args.workload]
+    if args.n or args.walkers:
+        wl = wl.with_(name=f"{wl.name}_n{args.n or wl.n}_w{args.walkers or wl.walkers}",
+                      n=args.n or wl.n, walkers=args.walkers or wl.walkers)
     p = abi.params_for(wl, threads=args.threads, variant=args.variant)
     dtype = "f32" if wl.precision == configs.FP32 else "f64"
     torch.cuda.set_device(0)

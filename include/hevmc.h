@@ -149,6 +149,34 @@ hevmc_status hevmc_sweep(const hevmc_params *p, void *coords, hevmc_walker_acc *
                          uint32_t sweep0, int32_t n_sweeps, uint32_t measure_start,
                          int32_t energy_every, void *stream);
 
+/* ---- Batched sweeps (serving: walkers of several requests in one launch) ---- */
+
+#define HEVMC_MAX_BATCH 16
+
+/* One request of a batched sweep: its parameters (n_walkers = its walkers)
+ * and where its sweep counters stand for this launch. */
+typedef struct {
+    hevmc_params params;
+    uint32_t sweep0;         /* index of the request's first sweep in this launch */
+    uint32_t measure_start;  /* as in hevmc_sweep                                  */
+    int32_t energy_every;    /* as in hevmc_sweep                                  */
+    int32_t reserved;        /* 0                                                  */
+} hevmc_request;
+
+/* hevmc_sweep for walker slots of up to HEVMC_MAX_BATCH requests that share
+ * N, precision, threads and variant (their density, b, step, seed and sweep
+ * counters may differ), n_sweeps sweeps each, in one launch.  Slot w of the
+ * device buffers coords [n_slots][3][N], acc [n_slots], rows [n_slots][N]
+ * (rows may be NULL) belongs to request map[2w] (an index into requests, or
+ * -1 for an unused slot, which the launch leaves untouched) and draws its
+ * random numbers as Philox walker id map[2w+1].  map: device int32
+ * [n_slots][2].  requests: host array, copied into the launch's arguments.  A
+ * request's result does not depend on which slots it occupies or which other
+ * requests share the launch.  Asynchronous on stream. */
+hevmc_status hevmc_sweep_batch(int32_t n_requests, const hevmc_request *requests, const int32_t *map,
+                               int32_t n_slots, void *coords, hevmc_walker_acc *acc, double *rows,
+                               int32_t n_sweeps, void *stream);
+
 /* Local energy of each walker's configuration (Sec. 2 local value of H).
  * coords: device [W][3][N]; out: device [W][6] doubles =
  * (E_L, V, T_PB, T_JF, T_F, U) with U = ln psi.  Asynchronous on stream. */

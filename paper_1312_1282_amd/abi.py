@@ -48,6 +48,19 @@ class Params(C.Structure):
     ]
 
 
+MAX_BATCH = 16
+
+
+class Request(C.Structure):
+    _fields_ = [
+        ("params", Params),
+        ("sweep0", C.c_uint32),
+        ("measure_start", C.c_uint32),
+        ("energy_every", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
 ACC_FIELDS = [
     "u_run", "v_run", "sum_e", "c_e", "sum_e2", "c_e2", "sum_v", "c_v", "sum_tpb", "c_tpb",
     "sum_tjf", "c_tjf", "sum_tf", "c_tf", "sum_vs", "c_vs",
@@ -65,7 +78,7 @@ assert C.sizeof(WalkerAcc) == ACC_BYTES
 
 EXPORTS = [
     "hevmc_box", "hevmc_footprint", "hevmc_init_walkers", "hevmc_sweep", "hevmc_local_energy",
-    "hevmc_move_delta", "hevmc_draw_moves", "hevmc_create", "hevmc_create_on", "hevmc_run",
+    "hevmc_move_delta", "hevmc_draw_moves", "hevmc_sweep_batch", "hevmc_create", "hevmc_create_on", "hevmc_run",
     "hevmc_sync", "hevmc_get_acc", "hevmc_get_coords", "hevmc_get_sweep", "hevmc_destroy",
     "hevmc_eval_config", "hevmc_last_error",
 ]
@@ -91,6 +104,7 @@ def lib():
             "hevmc_local_energy": [P, vp, vp, vp],
             "hevmc_move_delta": [P, vp, vp, vp, vp, vp],
             "hevmc_draw_moves": [P, C.c_uint32, vp, vp, vp, vp],
+            "hevmc_sweep_batch": [C.c_int32, C.POINTER(Request), vp, C.c_int32, vp, vp, vp, C.c_int32, vp],
             "hevmc_create": [P, vp, vp, C.POINTER(vp)],
             "hevmc_create_on": [P, vp, vp, vp, C.POINTER(vp)],
             "hevmc_run": [vp, C.c_int32, C.c_int32, C.c_int32],
@@ -233,6 +247,20 @@ def draw_moves(p, t, s_out, xi_out, delta_out, stream=None):
     _check(lib().hevmc_draw_moves(C.byref(p), int(t), _ptr(s_out, torch.int32, (W, n), "s_out"),
                                   _ptr(xi_out, torch.float64, (W, n), "xi_out"),
                                   _ptr(delta_out, torch.float64, (W, n, 3), "delta_out"), _stream(stream)))
+
+
+def sweep_batch(requests, walker_map, coords, acc, rows, n_sweeps, stream=None):
+    """hevmc_sweep_batch: requests is a ctypes array of Request sharing N and
+    precision; walker_map a [slots, 2] int32 device tensor (request index or
+    -1, Philox walker id); coords/acc/rows the class's slot buffers."""
+    torch = _torch()
+    p0 = requests[0].params
+    slots = walker_map.shape[0]
+    _check(lib().hevmc_sweep_batch(len(requests), requests, _ptr(walker_map, torch.int32, (slots, 2), "map"), slots,
+                                   _ptr(coords, coord_dtype(p0), (slots, 3, p0.n), "coords"),
+                                   _ptr(acc, None, (slots, ACC_BYTES), "acc"),
+                                   _ptr(rows, torch.float64, (slots, p0.n), "rows") if rows is not None else None,
+                                   int(n_sweeps), _stream(stream)))
 
 
 def acc_to_numpy(acc):

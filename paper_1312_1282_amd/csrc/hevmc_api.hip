@@ -94,17 +94,21 @@ hevmc_status check_params(const hevmc_params *p)
         return fail(HEVMC_EINVAL, "hbar2_over_m = %g must be finite and > 0", p->hbar2_over_m);
     if (!finite_pos(p->step_sigma))
         return fail(HEVMC_EINVAL, "step_sigma = %g must be finite and > 0", p->step_sigma);
-    if (p->threads != 0 && p->threads != 128 && p->threads != 256 && p->threads != 512 && p->threads != 1024)
-        return fail(HEVMC_EINVAL, "threads = %d must be 0, 128, 256, 512 or 1024", p->threads);
+    if (p->threads != 0 && p->threads != 64 && p->threads != 128 && p->threads != 256 && p->threads != 512 &&
+        p->threads != 1024)
+        return fail(HEVMC_EINVAL, "threads = %d must be 0, 64, 128, 256, 512 or 1024", p->threads);
     if (p->variant < HEVMC_VARIANT_AUTO || p->variant > HEVMC_VARIANT_ROWS)
         return fail(HEVMC_EINVAL, "variant = %d is not a hevmc_variant", p->variant);
     return HEVMC_OK;
 }
 
-// Threads per walker when the caller leaves the choice to the library: about
-// 8 atoms per lane, 2 to 8 waves.
+// Threads per walker when the caller leaves the choice to the library: one
+// wave per walker (four walkers per workgroup) up to 8 atoms per lane, else
+// about 8 atoms per lane, 2 to 8 waves.
 int default_threads(int n)
 {
+    if (n <= 64 * kRowsPerLane)
+        return 64;
     if (n <= 1024)
         return 128;
     if (n <= 3072)
@@ -134,6 +138,8 @@ size_t rows_lds_bytes(const hevmc_params *p)
     return rows_lds_offset(p->n, tsz) + (size_t)p->n * sizeof(double);
 }
 
+void make_kparams(const hevmc_params *p, KParams &k);
+
 // Launch plan: threads per walker, sweep variant and the dynamic LDS request.
 // The request is padded so that each compute unit holds r walkers, r the
 // largest divisor of ceil(W / CUs) whose walkers fit in its LDS: the walkers
@@ -147,26 +153,33 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L)
     if ((st = device_limits(d)) != HEVMC_OK)
         return st;
     const int threads = p->threads ? p->threads : default_threads(p->n);
-    const size_t stat = static_lds(threads);
+    const bool wave_mode = threads == 64;
+    // walkers per workgroup: one, or kWalkersPerGroup single-wave walkers
+    const int per_group = wave_mode ? kWalkersPerGroup : 1;
+    const size_t stat = wave_mode ? 64 : static_lds(threads);
     const size_t max_dyn = d.lds_per_block > stat ? d.lds_per_block - stat : 0;
     const size_t need_plain = lds_needed(p);
     const size_t need_rows = rows_lds_bytes(p);
-    if (need_plain > max_dyn)
+    const size_t align16 = 15;
+    if (need_plain > max_dyn || (wave_mode && per_group * ((need_plain + align16) & ~align16) > max_dyn))
         return fail(HEVMC_ENOFIT, "walker of %d atoms needs %zu B of LDS; a workgroup can have %zu B", p->n,
-                    need_plain, max_dyn);
-    const bool rows_ok = p->n <= kRowsPerLane * threads && need_rows <= max_dyn;
+                    need_plain * per_group, max_dyn);
+    const bool rows_ok = p->n <= kRowsPerLane * threads &&
+                         per_group * ((need_rows + align16) & ~align16) <= max_dyn;
     if (p->variant == HEVMC_VARIANT_ROWS && !rows_ok)
         return fail(HEVMC_ENOFIT, "row-sum sweep needs N <= %d x threads and %zu B of LDS per walker",
                     kRowsPerLane, need_rows);
     const bool use_rows = p->variant == HEVMC_VARIANT_ROWS || (p->variant == HEVMC_VARIANT_AUTO && rows_ok);
-    const size_t need = use_rows ? need_rows : need_plain;
+    const size_t walker_need = ((use_rows ? need_rows : need_plain) + align16) & ~align16;
+    const size_t need = walker_need * per_group;
     size_t lds = need;
-    // walkers a compute unit can hold: by LDS, and by waves (4 SIMDs, register
+    // workgroups a compute unit can hold: by LDS, and by waves (4 SIMDs, register
     // file shared by the waves of a SIMD)
-    const int waves_per_walker = threads / 64;
+    const int waves_per_group = threads / 64 * per_group;
     const int by_waves = 4 * waves_per_simd(sweep_vgprs(p->precision == HEVMC_FP32, threads, use_rows)) /
-                         waves_per_walker;
-    const int per_cu = (p->n_walkers + d.cus - 1) / d.cus;
+                         waves_per_group;
+    const int groups = (p->n_walkers + per_group - 1) / per_group;
+    const int per_cu = (groups + d.cus - 1) / d.cus;
     for (int r = per_cu; r >= 1; --r) {
         if (per_cu % r != 0)
             continue;
@@ -179,11 +192,24 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L)
             lds = even < max_dyn ? even : max_dyn;
         break;
     }
+    make_kparams(p, L.k);
+    L.p.n_walkers_grid = p->n_walkers;
+    L.threads = threads;
+    L.fp32 = p->precision == HEVMC_FP32;
+    L.rows = use_rows;
+    L.lds_bytes = lds;
+    L.walker_lds = walker_need;
+    L.stream = (hipStream_t)stream;
+    return HEVMC_OK;
+}
+
+// Kernel-side constants of a parameter set.
+void make_kparams(const hevmc_params *p, KParams &k)
+{
     const double Ld = box_side(p);
     const double h = 0.5 * Ld;
     const double b = p->b;
     const double q = b / h;
-    KParams &k = L.k;
     k.n = p->n;
     k.order = p->order;
     k.wid_base = p->walker_id_base;
@@ -201,13 +227,6 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L)
     k.h2f = (float)(h * h);
     k.c5f = (float)k.c5;
     k.u0f = (float)k.u0;
-    L.p.n_walkers_grid = p->n_walkers;
-    L.threads = threads;
-    L.fp32 = p->precision == HEVMC_FP32;
-    L.rows = use_rows;
-    L.lds_bytes = lds;
-    L.stream = (hipStream_t)stream;
-    return HEVMC_OK;
 }
 
 hevmc_status launched(hipError_t e, const char *what) { return e == hipSuccess ? HEVMC_OK : hip_fail(e, what); }
@@ -284,6 +303,49 @@ extern "C" hevmc_status hevmc_sweep(const hevmc_params *p, void *coords, hevmc_w
         return HEVMC_OK;
     return launched(launch_sweep(L, coords, acc, rows, sweep0, n_sweeps, measure_start, energy_every),
                     "sweep kernel launch");
+}
+
+extern "C" hevmc_status hevmc_sweep_batch(int32_t n_requests, const hevmc_request *requests, const int32_t *map,
+                                          int32_t n_slots, void *coords, hevmc_walker_acc *acc, double *rows,
+                                          int32_t n_sweeps, void *stream)
+{
+    if (n_requests < 1 || n_requests > HEVMC_MAX_BATCH)
+        return fail(HEVMC_EINVAL, "n_requests = %d must be in [1, %d]", n_requests, HEVMC_MAX_BATCH);
+    if (!requests || !map || !coords || !acc)
+        return fail(HEVMC_EINVAL, "requests, map, coords and acc must not be NULL");
+    if (n_slots < 1)
+        return fail(HEVMC_EINVAL, "n_slots = %d must be >= 1", n_slots);
+    if (n_sweeps < 0)
+        return fail(HEVMC_EINVAL, "n_sweeps = %d must be >= 0", n_sweeps);
+    const hevmc_params &p0 = requests[0].params;
+    BatchArgs b = {};
+    b.count = n_requests;
+    for (int r = 0; r < n_requests; ++r) {
+        const hevmc_request &q = requests[r];
+        hevmc_status st = check_params(&q.params);
+        if (st != HEVMC_OK)
+            return fail(st, "request %d: %s", r, g_err.c_str());
+        if (q.params.n != p0.n || q.params.precision != p0.precision || q.params.threads != p0.threads ||
+            q.params.variant != p0.variant)
+            return fail(HEVMC_EINVAL, "request %d differs from request 0 in n, precision, threads or variant", r);
+        if (q.energy_every < 0)
+            return fail(HEVMC_EINVAL, "request %d: energy_every = %d must be >= 0", r, q.energy_every);
+        if ((uint64_t)q.sweep0 + (uint64_t)n_sweeps > 0xFFFFFFFFull)
+            return fail(HEVMC_EINVAL, "request %d: sweep counter would pass 2^32 - 1", r);
+        make_kparams(&q.params, b.k[r]);
+        b.sweep0[r] = q.sweep0;
+        b.mstart[r] = q.measure_start;
+        b.m[r] = q.energy_every;
+    }
+    hevmc_params shape = p0;
+    shape.n_walkers = n_slots;
+    Launch L;
+    hevmc_status st = plan(&shape, stream, L);
+    if (st != HEVMC_OK)
+        return st;
+    if (n_sweeps == 0)
+        return HEVMC_OK;
+    return launched(launch_sweep_batch(L, b, map, n_slots, coords, acc, rows, n_sweeps), "batched sweep launch");
 }
 
 extern "C" hevmc_status hevmc_local_energy(const hevmc_params *p, const void *coords, double *out, void *stream)

@@ -14,11 +14,24 @@ namespace hevmc {
 // are kept in registers): N <= kRowsPerLane * threads.
 constexpr int kRowsPerLane = 8;
 
+// Walkers per workgroup of the one-wave-per-walker sweep (threads = 64).
+constexpr int kWalkersPerGroup = 4;
+
 // Byte offset of the row sums behind the coordinates in a walker's LDS.
 __host__ __device__ constexpr size_t rows_lds_offset(int n, size_t tsize)
 {
     return ((size_t)3 * (size_t)n * tsize + 15) & ~(size_t)15;
 }
+
+// Per-request constants of a batched sweep, passed by value in the kernel
+// arguments (at most HEVMC_MAX_BATCH requests per launch).
+struct BatchArgs {
+    KParams k[HEVMC_MAX_BATCH];
+    uint32_t sweep0[HEVMC_MAX_BATCH];
+    uint32_t mstart[HEVMC_MAX_BATCH];
+    int32_t m[HEVMC_MAX_BATCH];
+    int32_t count;
+};
 
 struct LaunchShape {
     int n_walkers_grid;  // workgroups (walkers) in the grid
@@ -31,12 +44,15 @@ struct Launch {
     int threads;        // threads per walker workgroup
     bool fp32;
     bool rows;          // row-sum variant of the sweep
-    size_t lds_bytes;   // dynamic LDS per workgroup
+    size_t lds_bytes;   // dynamic LDS per workgroup of the sweep kernel
+    size_t walker_lds;  // dynamic LDS of one walker (the per-walker kernels)
     hipStream_t stream;
 };
 
 hipError_t launch_sweep(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows, uint32_t sweep0,
                         int32_t nsw, uint32_t mstart, int32_t m);
+hipError_t launch_sweep_batch(const Launch &L, const BatchArgs &b, const int32_t *map, int32_t n_slots,
+                              void *coords, hevmc_walker_acc *acc, double *rows, int32_t nsw);
 hipError_t launch_local_energy(const Launch &L, const void *coords, double *out);
 hipError_t launch_init(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows, int fcc, int nc,
                        double a_lat);

@@ -32,16 +32,37 @@ namespace hevmc {
 
 __device__ __forceinline__ int readlane_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
-// Sum of NV doubles over the workgroup; every thread gets the same totals.
-// buf must hold NW*NV doubles; it is free again when the function returns.
+// Synchronise the NT threads of one walker: the workgroup, or, when a walker
+// is a single wave (NT = 64, several walkers per workgroup), the wave, whose
+// LDS accesses are ordered by wavefront-scope fences.
+template <int NT>
+__device__ __forceinline__ void walker_sync()
+{
+    if constexpr (NT == 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// Thread index within a walker's NT threads.
+template <int NT>
+__device__ __forceinline__ int walker_tid() { return (int)(threadIdx.x & (NT - 1)); }
+
+// Sum of NV doubles over a walker's NT threads; every thread gets the same
+// totals.  For NT > 64, buf must hold NW*NV doubles (free again on return).
 template <int NT, int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double *buf)
 {
     constexpr int NW = NT / 64;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = walker_tid<NT>() >> 6;
 #pragma unroll
     for (int q = 0; q < NV; ++q)
         v[q] = wave_sum(v[q]);
+    if constexpr (NW == 1)
+        return;
     if (lane == 0) {
 #pragma unroll
         for (int q = 0; q < NV; ++q)
@@ -69,7 +90,7 @@ __device__ void local_energy_pass(const KParams &p, const T *sx, const T *sy, co
 {
     const int n = p.n;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};   // sum |G_i|^2, sum L_i, sum V_i, sum U_i
-    for (int i = threadIdx.x; i < n; i += NT) {
+    for (int i = walker_tid<NT>(); i < n; i += NT) {
         const T xi = sx[i], yi = sy[i], zi = sz[i];
         double gx = 0, gy = 0, gz = 0, li = 0, vi = 0, ui = 0;
         for (int j = 0; j < n; ++j) {
@@ -111,7 +132,7 @@ template <typename T, int NT>
 __device__ void row_pass(const KParams &p, const T *sx, const T *sy, const T *sz, double *rows)
 {
     const int n = p.n;
-    for (int i = threadIdx.x; i < n; i += NT) {
+    for (int i = walker_tid<NT>(); i < n; i += NT) {
         const T xi = sx[i], yi = sy[i], zi = sz[i];
         double ui = 0.0;
         for (int j = 0; j < n; ++j) {
@@ -134,7 +155,7 @@ __device__ __forceinline__ void move_partial(const KParams &p, const T *sx, cons
                                              double &du, double &dv)
 {
     const int n = p.n;
-    for (int i = threadIdx.x; i < n; i += NT) {
+    for (int i = walker_tid<NT>(); i < n; i += NT) {
         const T xi = sx[i], yi = sy[i], zi = sz[i];
         const T ax = min_image(ox - xi, p), ay = min_image(oy - yi, p), az_ = min_image(oz - zi, p);
         const T bx = min_image(nx - xi, p), by = min_image(ny - yi, p), bz = min_image(nz - zi, p);
@@ -174,35 +195,30 @@ __device__ void fcc_site(const KParams &p, uint32_t wid, int pidx, int nc, doubl
 }
 
 // --------------------------------------------------------------------------
-// The sweep kernel (hevmc_sweep).  Grid: one workgroup of NT threads per walker.
-// Dynamic LDS: x, y, z (T) and, for ROWS, the row sums (double) at
-// rows_lds_offset(n, sizeof(T)).  rows_hbm ([W][N] doubles) may be null.
+// One walker's sweeps (the body of the sweep kernels).  Dynamic LDS: x, y, z
+// (T) and, for ROWS, the row sums (double) at rows_lds_offset(n, sizeof(T)).
+// g: the walker's coordinates [3][N]; accp: its accumulators; rg: its row sums
+// in HBM ([N] doubles) or null.  For NT = 64 the walker is one wave and red,
+// rsl, ebuf are not used.
 template <typename T, int NT, bool ROWS>
-__global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
-                                              hevmc_walker_acc *__restrict__ accs,
-                                              double *__restrict__ rows_hbm, uint32_t sweep0, int32_t nsw,
-                                              uint32_t mstart, int32_t m)
+__device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *__restrict__ g,
+                                             hevmc_walker_acc *__restrict__ accp, double *__restrict__ rg,
+                                             uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t m,
+                                             unsigned char *smem_raw, double (*red)[NT / 64][2], double *rsl,
+                                             double *ebuf)
 {
     constexpr int NW = NT / 64;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[2][NW][2];
-    __shared__ double rsl[2];
-    __shared__ double ebuf[NW * 4];
     T *sx = reinterpret_cast<T *>(smem_raw);
     const int n = p.n;
     T *sy = sx + n, *sz = sy + n;
     double *ru = reinterpret_cast<double *>(smem_raw + rows_lds_offset(n, sizeof(T)));
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int w = blockIdx.x;
-    const uint32_t wid = p.wid_base + (uint32_t)w;
+    const int tid = walker_tid<NT>(), lane = tid & 63, wave = tid >> 6;
 
-    T *g = coords + (size_t)w * 3 * (size_t)n;
     for (int i = tid; i < 3 * n; i += NT)
         sx[i] = g[i];
-    hevmc_walker_acc a = accs[w];
+    hevmc_walker_acc a = *accp;
     double u_run = a.u_run, v_run = a.v_run;
     int64_t n_acc = 0, n_try = 0, n_samp = 0, n_swm = 0;
-    double *rg = rows_hbm ? rows_hbm + (size_t)w * (size_t)n : nullptr;
     if constexpr (ROWS) {
         bool valid = false;
         if (rg) {
@@ -216,11 +232,11 @@ __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
             block_sum<NT, 2>(c, ebuf);
             valid = fabs(0.5 * c[0] - u_run) <= 1e-9 * (0.5 * c[1] + 1.0);
         }
-        __syncthreads();
+        walker_sync<NT>();
         if (!valid)
             row_pass<T, NT>(p, sx, sy, sz, ru);
     } else {
-        __syncthreads();
+        walker_sync<NT>();
     }
 
     int last_s = -1;          // atom accepted in the previous micro-update
@@ -273,22 +289,31 @@ __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
                     }
                     const double w0 = wave_sum(su);
                     const double w1 = (last_s >= 0) ? wave_sum(dv_pend) : 0.0;
-                    if (lane == 0) {
-                        red[k & 1][wave][0] = w0;
-                        red[k & 1][wave][1] = w1;
-                    }
-                    if (owner)
-                        rsl[k & 1] = ru[s];
-                    __syncthreads();
-                    double SU = 0.0, DVP = 0.0;
+                    double SU = 0.0, DVP = 0.0, RS;
+                    if constexpr (NW == 1) {
+                        // one wave per walker: the butterfly already gave every
+                        // lane the totals, and the owner's row is visible in-wave
+                        SU = w0;
+                        DVP = w1;
+                        RS = ru[s];
+                    } else {
+                        if (lane == 0) {
+                            red[k & 1][wave][0] = w0;
+                            red[k & 1][wave][1] = w1;
+                        }
+                        if (owner)
+                            rsl[k & 1] = ru[s];
+                        __syncthreads();
 #pragma unroll
-                    for (int q = 0; q < NW; ++q) {
-                        SU += red[k & 1][q][0];
-                        DVP += red[k & 1][q][1];
+                        for (int q = 0; q < NW; ++q) {
+                            SU += red[k & 1][q][0];
+                            DVP += red[k & 1][q][1];
+                        }
+                        RS = rsl[k & 1];
                     }
                     v_run += DVP;
                     dv_pend = 0.0;
-                    const double DU = SU - rsl[k & 1];
+                    const double DU = SU - RS;
                     const bool accept = metropolis_accept(DU, xi);
                     if (measured) {
                         n_try += 1;
@@ -328,16 +353,21 @@ __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
                     move_partial<T, NT>(p, sx, sy, sz, s, ox, oy, oz, nx, ny, nz, du, dv);
                     du = wave_sum(du);
                     dv = wave_sum(dv);
-                    if (lane == 0) {
-                        red[k & 1][wave][0] = du;
-                        red[k & 1][wave][1] = dv;
-                    }
-                    __syncthreads();
                     double DU = 0.0, DV = 0.0;
+                    if constexpr (NW == 1) {
+                        DU = du;
+                        DV = dv;
+                    } else {
+                        if (lane == 0) {
+                            red[k & 1][wave][0] = du;
+                            red[k & 1][wave][1] = dv;
+                        }
+                        __syncthreads();
 #pragma unroll
-                    for (int q = 0; q < NW; ++q) {
-                        DU += red[k & 1][q][0];
-                        DV += red[k & 1][q][1];
+                        for (int q = 0; q < NW; ++q) {
+                            DU += red[k & 1][q][0];
+                            DV += red[k & 1][q][1];
+                        }
                     }
                     const bool accept = metropolis_accept(DU, xi);
                     if (measured) {
@@ -367,7 +397,7 @@ __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
         }
         if (measured) {
             if (m > 0 && (t - mstart + 1) % (uint32_t)m == 0) {
-                __syncthreads();
+                walker_sync<NT>();
                 double el[6];
                 local_energy_pass<T, NT>(p, sx, sy, sz, ebuf, el, ROWS ? ru : nullptr);
                 if (tid == 0) {
@@ -388,7 +418,7 @@ __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
             n_swm += 1;
         }
     }
-    __syncthreads();
+    walker_sync<NT>();
     for (int i = tid; i < 3 * n; i += NT)
         g[i] = sx[i];
     if constexpr (ROWS) {
@@ -403,8 +433,92 @@ __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
         a.n_sweeps_meas += n_swm;
         a.n_acc += n_acc;
         a.n_try += n_try;
-        accs[w] = a;
+        *accp = a;
     }
+}
+
+// The sweep kernel (hevmc_sweep).  Grid: one workgroup of NT threads per walker.
+template <typename T, int NT, bool ROWS>
+__global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
+                                              hevmc_walker_acc *__restrict__ accs,
+                                              double *__restrict__ rows_hbm, uint32_t sweep0, int32_t nsw,
+                                              uint32_t mstart, int32_t m)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[2][NT / 64][2];
+    __shared__ double rsl[2];
+    __shared__ double ebuf[NT / 64 * 4];
+    const int w = blockIdx.x;
+    const size_t n = (size_t)p.n;
+    sweep_walker<T, NT, ROWS>(p, p.wid_base + (uint32_t)w, coords + (size_t)w * 3 * n, accs + w,
+                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, sweep0, nsw, mstart, m, smem_raw,
+                              red, rsl, ebuf);
+}
+
+// The batched sweep kernel (hevmc_sweep_batch): walker slots of several
+// requests with the same N and precision in one grid.  map[2w] is the slot's
+// request (or -1 for a free slot, which does nothing), map[2w+1] its Philox
+// walker id; each request's constants and sweep counters come from the
+// kernel arguments.
+template <typename T, int NT, bool ROWS>
+__global__ __launch_bounds__(NT) void k_sweep_batch(BatchArgs b, const int32_t *__restrict__ map,
+                                                    T *__restrict__ coords, hevmc_walker_acc *__restrict__ accs,
+                                                    double *__restrict__ rows_hbm, int32_t nsw)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[2][NT / 64][2];
+    __shared__ double rsl[2];
+    __shared__ double ebuf[NT / 64 * 4];
+    const int w = blockIdx.x;
+    const int r = map[2 * w];
+    if (r < 0 || r >= b.count)
+        return;
+    const uint32_t wid = (uint32_t)map[2 * w + 1];
+    const size_t n = (size_t)b.k[r].n;
+    sweep_walker<T, NT, ROWS>(b.k[r], wid, coords + (size_t)w * 3 * n, accs + w,
+                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, b.sweep0[r], nsw, b.mstart[r],
+                              b.m[r], smem_raw, red, rsl, ebuf);
+}
+
+// One wave per walker, kWalkersPerGroup walkers per workgroup (small N): the
+// walkers of a workgroup share nothing but the compute unit; each has its own
+// LDS region of walker_lds bytes and never waits for the others.
+template <typename T, bool ROWS>
+__global__ __launch_bounds__(64 * kWalkersPerGroup) void k_sweep_wave(KParams p, T *__restrict__ coords,
+                                                                      hevmc_walker_acc *__restrict__ accs,
+                                                                      double *__restrict__ rows_hbm, int32_t W,
+                                                                      uint32_t walker_lds, uint32_t sweep0,
+                                                                      int32_t nsw, uint32_t mstart, int32_t m)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int wv = threadIdx.x >> 6;
+    const int w = blockIdx.x * kWalkersPerGroup + wv;
+    if (w >= W)
+        return;
+    const size_t n = (size_t)p.n;
+    sweep_walker<T, 64, ROWS>(p, p.wid_base + (uint32_t)w, coords + (size_t)w * 3 * n, accs + w,
+                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, sweep0, nsw, mstart, m,
+                              smem_raw + (size_t)wv * walker_lds, nullptr, nullptr, nullptr);
+}
+
+template <typename T, bool ROWS>
+__global__ __launch_bounds__(64 * kWalkersPerGroup) void k_sweep_batch_wave(
+    BatchArgs b, const int32_t *__restrict__ map, T *__restrict__ coords, hevmc_walker_acc *__restrict__ accs,
+    double *__restrict__ rows_hbm, int32_t n_slots, uint32_t walker_lds, int32_t nsw)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int wv = threadIdx.x >> 6;
+    const int w = blockIdx.x * kWalkersPerGroup + wv;
+    if (w >= n_slots)
+        return;
+    const int r = map[2 * w];
+    if (r < 0 || r >= b.count)
+        return;
+    const uint32_t wid = (uint32_t)map[2 * w + 1];
+    const size_t n = (size_t)b.k[r].n;
+    sweep_walker<T, 64, ROWS>(b.k[r], wid, coords + (size_t)w * 3 * n, accs + w,
+                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, b.sweep0[r], nsw, b.mstart[r], b.m[r],
+                              smem_raw + (size_t)wv * walker_lds, nullptr, nullptr, nullptr);
 }
 
 // Local energies of the W configurations (hevmc_local_energy).
@@ -535,6 +649,27 @@ template <typename T, int NT>
 static hipError_t launch_sweep_t(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows,
                                  uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t m)
 {
+    if constexpr (NT == 64) {
+        const int groups = (L.p.n_walkers_grid + kWalkersPerGroup - 1) / kWalkersPerGroup;
+        const uint32_t wl = (uint32_t)L.walker_lds;
+        if (L.rows) {
+            auto kern = k_sweep_wave<T, true>;
+            hipError_t e = allow_lds(kern, L.lds_bytes);
+            if (e != hipSuccess)
+                return e;
+            hipLaunchKernelGGL(kern, dim3(groups), dim3(64 * kWalkersPerGroup), L.lds_bytes, L.stream, L.k,
+                               (T *)coords, acc, rows, L.p.n_walkers_grid, wl, sweep0, nsw, mstart, m);
+        } else {
+            auto kern = k_sweep_wave<T, false>;
+            hipError_t e = allow_lds(kern, L.lds_bytes);
+            if (e != hipSuccess)
+                return e;
+            hipLaunchKernelGGL(kern, dim3(groups), dim3(64 * kWalkersPerGroup), L.lds_bytes, L.stream, L.k,
+                               (T *)coords, acc, (double *)nullptr, L.p.n_walkers_grid, wl, sweep0, nsw, mstart,
+                               m);
+        }
+        return hipGetLastError();
+    }
     if (L.rows) {
         auto kern = k_sweep<T, NT, true>;
         hipError_t e = allow_lds(kern, L.lds_bytes);
@@ -554,13 +689,55 @@ static hipError_t launch_sweep_t(const Launch &L, void *coords, hevmc_walker_acc
 }
 
 template <typename T, int NT>
+static hipError_t launch_batch_t(const Launch &L, const BatchArgs &b, const int32_t *map, int32_t n_slots,
+                                 void *coords, hevmc_walker_acc *acc, double *rows, int32_t nsw)
+{
+    if constexpr (NT == 64) {
+        const int groups = (n_slots + kWalkersPerGroup - 1) / kWalkersPerGroup;
+        const uint32_t wl = (uint32_t)L.walker_lds;
+        if (L.rows) {
+            auto kern = k_sweep_batch_wave<T, true>;
+            hipError_t e = allow_lds(kern, L.lds_bytes);
+            if (e != hipSuccess)
+                return e;
+            hipLaunchKernelGGL(kern, dim3(groups), dim3(64 * kWalkersPerGroup), L.lds_bytes, L.stream, b, map,
+                               (T *)coords, acc, rows, n_slots, wl, nsw);
+        } else {
+            auto kern = k_sweep_batch_wave<T, false>;
+            hipError_t e = allow_lds(kern, L.lds_bytes);
+            if (e != hipSuccess)
+                return e;
+            hipLaunchKernelGGL(kern, dim3(groups), dim3(64 * kWalkersPerGroup), L.lds_bytes, L.stream, b, map,
+                               (T *)coords, acc, (double *)nullptr, n_slots, wl, nsw);
+        }
+        return hipGetLastError();
+    }
+    if (L.rows) {
+        auto kern = k_sweep_batch<T, NT, true>;
+        hipError_t e = allow_lds(kern, L.lds_bytes);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(kern, dim3(n_slots), dim3(NT), L.lds_bytes, L.stream, b, map, (T *)coords, acc, rows,
+                           nsw);
+    } else {
+        auto kern = k_sweep_batch<T, NT, false>;
+        hipError_t e = allow_lds(kern, L.lds_bytes);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(kern, dim3(n_slots), dim3(NT), L.lds_bytes, L.stream, b, map, (T *)coords, acc,
+                           (double *)nullptr, nsw);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int NT>
 static hipError_t launch_energy_t(const Launch &L, const void *coords, double *out)
 {
     auto kern = k_local_energy<T, NT>;
-    hipError_t e = allow_lds(kern, L.lds_bytes);
+    hipError_t e = allow_lds(kern, L.walker_lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k,
+    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.walker_lds, L.stream, L.k,
                        (const T *)coords, out);
     return hipGetLastError();
 }
@@ -570,10 +747,10 @@ static hipError_t launch_init_t(const Launch &L, void *coords, hevmc_walker_acc 
                                 int nc, double a_lat)
 {
     auto kern = k_init<T, NT>;
-    hipError_t e = allow_lds(kern, L.lds_bytes);
+    hipError_t e = allow_lds(kern, L.walker_lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k, (T *)coords, acc,
+    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.walker_lds, L.stream, L.k, (T *)coords, acc,
                        rows, fcc, nc, a_lat);
     return hipGetLastError();
 }
@@ -583,10 +760,10 @@ static hipError_t launch_delta_t(const Launch &L, const void *coords, const int3
                                  double *out)
 {
     auto kern = k_move_delta<T, NT>;
-    hipError_t e = allow_lds(kern, L.lds_bytes);
+    hipError_t e = allow_lds(kern, L.walker_lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k,
+    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.walker_lds, L.stream, L.k,
                        (const T *)coords, s, d, out);
     return hipGetLastError();
 }
@@ -596,6 +773,7 @@ static hipError_t launch_delta_t(const Launch &L, const void *coords, const int3
     do {                                                                               \
         if (L.fp32) {                                                                  \
             switch (L.threads) {                                                       \
+            case 64: return FN<float, 64>(L, __VA_ARGS__);                            \
             case 128: return FN<float, 128>(L, __VA_ARGS__);                          \
             case 256: return FN<float, 256>(L, __VA_ARGS__);                          \
             case 512: return FN<float, 512>(L, __VA_ARGS__);                          \
@@ -603,6 +781,7 @@ static hipError_t launch_delta_t(const Launch &L, const void *coords, const int3
             }                                                                          \
         } else {                                                                       \
             switch (L.threads) {                                                       \
+            case 64: return FN<double, 64>(L, __VA_ARGS__);                           \
             case 128: return FN<double, 128>(L, __VA_ARGS__);                         \
             case 256: return FN<double, 256>(L, __VA_ARGS__);                         \
             case 512: return FN<double, 512>(L, __VA_ARGS__);                         \
@@ -623,6 +802,10 @@ int sweep_vgprs(bool fp32, int threads, bool rows)
 {
     const void *f = nullptr;
     switch (threads) {
+    case 64:
+        f = fp32 ? (rows ? (const void *)k_sweep_wave<float, true> : (const void *)k_sweep_wave<float, false>)
+                 : (rows ? (const void *)k_sweep_wave<double, true> : (const void *)k_sweep_wave<double, false>);
+        break;
     case 128: f = fp32 ? sweep_fn<float, 128>(rows) : sweep_fn<double, 128>(rows); break;
     case 256: f = fp32 ? sweep_fn<float, 256>(rows) : sweep_fn<double, 256>(rows); break;
     case 512: f = fp32 ? sweep_fn<float, 512>(rows) : sweep_fn<double, 512>(rows); break;
@@ -639,6 +822,12 @@ hipError_t launch_sweep(const Launch &L, void *coords, hevmc_walker_acc *acc, do
                         int32_t nsw, uint32_t mstart, int32_t m)
 {
     HEVMC_DISPATCH(launch_sweep_t, coords, acc, rows, sweep0, nsw, mstart, m);
+}
+
+hipError_t launch_sweep_batch(const Launch &L, const BatchArgs &b, const int32_t *map, int32_t n_slots,
+                              void *coords, hevmc_walker_acc *acc, double *rows, int32_t nsw)
+{
+    HEVMC_DISPATCH(launch_batch_t, b, map, n_slots, coords, acc, rows, nsw);
 }
 
 hipError_t launch_local_energy(const Launch &L, const void *coords, double *out)

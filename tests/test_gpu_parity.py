@@ -52,7 +52,7 @@ def _dev(x, dtype=torch.float64):
 # ---------------------------------------------------------------------------
 # per-configuration quantities
 
-@pytest.mark.parametrize("n,threads", [(2, 128), (4, 128), (27, 256), (108, 128), (500, 128), (500, 512),
+@pytest.mark.parametrize("n,threads", [(2, 64), (4, 128), (27, 256), (108, 64), (108, 128), (500, 64), (500, 512),
                                        (1100, 1024), (2048, 256), (2048, 512)])
 def test_move_sums_fp64(n, threads):
     W = 6
@@ -71,8 +71,8 @@ def test_move_sums_fp64(n, threads):
         assert within(out[w, 1], dv, sv, 1e-12), (w, out[w, 1], dv, sv)
 
 
-@pytest.mark.parametrize("n,threads", [(2, 128), (4, 128), (27, 128), (108, 256), (500, 128), (1100, 1024),
-                                       (2048, 256), (4000, 512)])
+@pytest.mark.parametrize("n,threads", [(2, 64), (4, 128), (27, 128), (108, 64), (108, 256), (500, 128),
+                                       (1100, 1024), (2048, 256), (4000, 512)])
 def test_local_energy_fp64(n, threads):
     W = 3
     s_ = osys(n)
@@ -235,7 +235,7 @@ def test_lockstep_without_energy_refresh(variant):
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
-@pytest.mark.parametrize("threads", [128, 256])
+@pytest.mark.parametrize("threads", [64, 128, 256])
 def test_lockstep_sequential_order_and_threads(variant, threads):
     n, W = 256, 3
     p = gparams(n, W, threads=threads, order=1, seed=9, wbase=40, variant=variant)
@@ -247,9 +247,10 @@ def test_lockstep_sequential_order_and_threads(variant, threads):
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_split_launches_bitwise_identical(variant):
-    n, W = 256, 4
-    p = gparams(n, W, seed=3, variant=variant)
+@pytest.mark.parametrize("threads", [64, 128])
+def test_split_launches_bitwise_identical(variant, threads):
+    n, W = 256, 5
+    p = gparams(n, W, seed=3, variant=variant, threads=threads)
     x1, a1 = _gpu_chain(p, [10], 2, 3)
     x2, a2 = _gpu_chain(p, [3, 4, 3], 2, 3)
     assert np.array_equal(x1, x2)

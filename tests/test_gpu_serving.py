@@ -1,0 +1,97 @@
+"""GPU tests of the batched sweep and the continuous-batching server: a
+request's result is the same alone and in a mix, bit for bit."""
+import numpy as np
+import pytest
+
+from paper_1312_1282_amd import abi, configs, serving
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _req(rid, n, W, precision, density, b, seed):
+    return serving.Request(rid=rid, arrival=0.0, n=n, walkers=W, precision=precision, density=density, b=b,
+                           seed=seed)
+
+
+@pytest.mark.parametrize("precision", [abi.FP64, abi.FP32])
+def test_batched_launch_equals_single_requests(precision):
+    """Three requests with the same N and precision but their own density, b
+    and seed share slot pools with gaps; after three launches of 7 sweeps each
+    (the first equilibration only) every request equals its own hevmc_sweep run."""
+    n = 256
+    reqs = [_req(0, n, 5, precision, 0.0190, 2.6, 11), _req(1, n, 3, precision, 0.0220, 3.0, 12),
+            _req(2, n, 4, precision, 0.0255, 3.3, 13)]
+    slots, starts = 20, [1, 8, 14]
+    shape = abi.make_params(n, slots, precision=precision)
+    coords, acc = abi.alloc_state(shape)
+    rows = abi.alloc_rows(shape)
+    wmap = np.full((slots, 2), -1, np.int32)
+    for k, (r, a) in enumerate(zip(reqs, starts)):
+        p = r.params()
+        abi.init_walkers(p, coords[a:a + r.walkers], acc[a:a + r.walkers], rows=rows[a:a + r.walkers])
+        wmap[a:a + r.walkers, 0] = k
+        wmap[a:a + r.walkers, 1] = np.arange(r.walkers)
+    dmap = torch.from_numpy(wmap).cuda()
+    t = 0
+    for q in range(3):
+        arr = (abi.Request * 3)()
+        for k, r in enumerate(reqs):
+            arr[k].params = r.params()
+            arr[k].sweep0 = t
+            arr[k].measure_start = 7
+            arr[k].energy_every = 2
+        abi.sweep_batch(arr, dmap, coords, acc, rows, 7)
+        t += 7
+    torch.cuda.synchronize()
+    xb = coords.cpu().numpy()
+    ab = abi.acc_to_numpy(acc)
+    for r, a in zip(reqs, starts):
+        p = r.params()
+        c1, a1 = abi.alloc_state(p)
+        r1 = abi.alloc_rows(p)
+        abi.init_walkers(p, c1, a1, rows=r1)
+        for q in range(3):
+            abi.sweep(p, c1, a1, 7 * q, 7, 7, 2, rows=r1)
+        torch.cuda.synchronize()
+        assert np.array_equal(c1.cpu().numpy(), xb[a:a + r.walkers])
+        assert abi.acc_to_numpy(a1).tobytes() == ab[a:a + r.walkers].tobytes()
+    # unused slots untouched
+    assert np.all(ab["n_try"][[0, 6, 7, 11, 12, 13, 18, 19]] == 0)
+
+
+def test_server_result_same_alone_and_in_mix():
+    """Requests of two classes served together (sharing pools and launches)
+    end with the same accumulators, bit for bit, and after the same number of
+    sweeps as each served alone."""
+    mk = lambda: [_req(0, 108, 64, abi.FP64, 0.0200, 2.8, 21), _req(1, 108, 96, abi.FP64, 0.0240, 3.1, 22),
+                  _req(2, 256, 64, abi.FP32, 0.0219, 2.9, 23), _req(3, 108, 80, abi.FP32, 0.0210, 3.0, 24)]
+    kw = dict(target_se=4e-3, equil=20, check_every=10, min_samples=2, quantum=5)
+    mix = serving.Server(**kw).run(mk(), realtime=False)
+    for r in mix:
+        assert r.done is not None and r.rejected is None
+    for k in range(4):
+        alone = serving.Server(**kw).run([mk()[k]], realtime=False)[0]
+        assert alone.sweeps == mix[k].sweeps
+        assert alone.result.tobytes() == mix[k].result.tobytes()
+        assert alone.se <= 4e-3
+
+
+def test_server_rejects_walkers_that_do_not_fit():
+    big = _req(0, 10976, 8, abi.FP64, 0.02186, 2.94, 1)    # FP64 walker of 263 KB: no workgroup can hold it
+    small = _req(1, 108, 64, abi.FP64, 0.02186, 2.94, 2)
+    out = serving.Server(target_se=5e-3, equil=10, check_every=10, min_samples=2, quantum=5).run(
+        [big, small], realtime=False)
+    assert out[0].rejected and "ENOFIT" in out[0].rejected
+    assert out[1].done is not None
+
+
+def test_request_stream_recipe():
+    reqs = serving.request_stream(200)
+    gaps = np.diff([0.0] + [r.arrival for r in reqs])
+    assert abs(gaps.mean() - 1 / configs.SERVE_RATE) < 0.2 / configs.SERVE_RATE
+    assert {r.n for r in reqs} == set(configs.SERVE_N)
+    assert all(64 <= r.walkers <= 512 for r in reqs)
+    assert all(configs.SERVE_RHO[0] <= r.density <= configs.SERVE_RHO[1] for r in reqs)
+    assert all(configs.SERVE_B[0] <= r.b <= configs.SERVE_B[1] for r in reqs)
+    assert {r.precision for r in reqs} == {abi.FP64, abi.FP32}
