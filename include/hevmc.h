@@ -87,8 +87,9 @@ typedef struct {
     double step_sigma;       /* std. deviation of each Cartesian move component (A), > 0 */
     uint64_t seed;           /* Philox key: (low 32 bits, high 32 bits)                   */
     uint32_t walker_id_base; /* walker w uses Philox walker id walker_id_base + w         */
-    int32_t threads;         /* threads per walker: 0 = library choice, else 128, 256,
-                                512 or 1024                                                */
+    int32_t threads;         /* threads per walker: 0 = library choice, else 64, 128,
+                                256, 512 or 1024 (64: one wavefront per walker, four
+                                walkers per workgroup)                                     */
     int32_t variant;         /* hevmc_variant                                             */
 } hevmc_params;
 
@@ -124,7 +125,8 @@ hevmc_status hevmc_footprint(const hevmc_params *p, size_t *lds_bytes_per_walker
  * otherwise coords must already hold valid positions.  Then sets u_run, v_run
  * of every walker from a full O(N^2) evaluation, zeroes all accumulators and,
  * if rows is not NULL, fills rows ([W][N] doubles, device) with each atom's
- * row sum sum_{j != i} u(r_ij) for later hevmc_sweep calls.
+ * row sum sum_{j != i} u(r_ij) for later hevmc_sweep calls.  A walker with a
+ * non-finite coordinate gets u_run = v_run = NaN.
  * coords, acc: device.  Asynchronous on stream. */
 hevmc_status hevmc_init_walkers(const hevmc_params *p, void *coords, hevmc_walker_acc *acc,
                                 double *rows, int32_t fcc_start, void *stream);
@@ -143,8 +145,10 @@ hevmc_status hevmc_init_walkers(const hevmc_params *p, void *coords, hevmc_walke
  * between calls (filled by hevmc_init_walkers or a previous hevmc_sweep on the
  * same walkers); the kernel checks sum_i R_i = 2 u_run and recomputes the rows
  * when the buffer is NULL or disagrees, an O(N^2) pass per walker.  Ignored by
- * the PLAIN variant.  Requires sweep0 + n_sweeps <= 0xFFFFFFFF.  Asynchronous
- * on stream. */
+ * the PLAIN variant.  A walker with a non-finite coordinate ends the call with
+ * u_run = v_run = NaN (its pairs would otherwise drop out of every sum
+ * unnoticed).  Requires sweep0 + n_sweeps <= 0xFFFFFFFF.  Asynchronous on
+ * stream. */
 hevmc_status hevmc_sweep(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
                          uint32_t sweep0, int32_t n_sweeps, uint32_t measure_start,
                          int32_t energy_every, void *stream);

@@ -6,6 +6,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -45,12 +47,36 @@ struct DeviceLimits {
     size_t lds_per_cu = 0;
 };
 
+hevmc_status device_limits_query(int dev, DeviceLimits &d);
+
+// Limits of the current device, queried once per device.
 hevmc_status device_limits(DeviceLimits &d)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess)
         return hip_fail(e, "hipGetDevice");
+    static std::mutex mu;
+    static std::map<int, DeviceLimits> known;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = known.find(dev);
+        if (it != known.end()) {
+            d = it->second;
+            return HEVMC_OK;
+        }
+    }
+    hevmc_status st = device_limits_query(dev, d);
+    if (st == HEVMC_OK) {
+        std::lock_guard<std::mutex> g(mu);
+        known[dev] = d;
+    }
+    return st;
+}
+
+hevmc_status device_limits_query(int dev, DeviceLimits &d)
+{
+    hipError_t e;
     int v = 0;
     if ((e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
         return hip_fail(e, "hipDeviceGetAttribute(MultiprocessorCount)");

@@ -112,28 +112,24 @@ __device__ __forceinline__ float min_image(float d, const KParams &p) { return d
 // device math library are correctly rounded or within an ulp but expand to long
 // instruction sequences; these use the hardware estimates with Newton steps.
 
-// 1/x: hardware reciprocal estimate refined by two Newton steps
-// (y <- y + y (1 - x y)); relative error at the rounding level.
+// 1/x: hardware reciprocal estimate refined by one Newton step
+// (y <- y + y (1 - x y)).  On gfx950 the estimate's relative error is below
+// 5e-8 and one step brings it below 3e-15 (measured over 1e-2 <= x <= 1e4),
+// three orders inside the 1e-12 tolerance the sums are held to.
 __device__ __forceinline__ double rcp_nr(double x)
 {
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
+    const double y = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, y, 1.0);
     return fma(y, e, y);
 }
 
-// 1/sqrt(x): hardware estimate refined by two Newton steps
-// (y <- y + (y/2)(1 - x y^2)).
+// 1/sqrt(x): hardware estimate refined by one Newton step
+// (y <- y + (y/2)(1 - x y^2)); below 5e-15 relative after the step.
 __device__ __forceinline__ double rsq_nr(double x)
 {
-    double y = __builtin_amdgcn_rsq(x);
-    double h = 0.5 * y;
-    double e = fma(-(x * y), y, 1.0);
-    y = fma(h, e, y);
-    h = 0.5 * y;
-    e = fma(-(x * y), y, 1.0);
-    return fma(h, e, y);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-(x * y), y, 1.0);
+    return fma(0.5 * y, e, y);
 }
 
 // e^a for a <= 0 (both exponentials of the potential have non-positive
@@ -207,6 +203,17 @@ __device__ __forceinline__ double pair_u_ri(const KParams &p, double r2, double 
     return r2 <= p.h2 ? uu : 0.0;
 }
 
+// u(r) for a pair that counts if `keep` (the moved atom itself does not):
+// zero beyond the cutoff or when !keep, with one select for both.
+__device__ __forceinline__ double pair_u_in(const KParams &p, double r2, double ri, bool keep)
+{
+    const double r = r2 * ri;
+    const double rpi = rcp_nr(p.L - r);
+    const double ri2 = ri * ri, rpi2 = rpi * rpi;
+    const double uu = fma(p.c5, fma(ri2 * ri2, ri, rpi2 * rpi2 * rpi), p.u0);
+    return (keep && r2 <= p.h2) ? uu : 0.0;
+}
+
 // FP64: V(r) alone, given r^2 and 1/r.
 __device__ __forceinline__ double pair_v_ri(const KParams &p, double r2, double ri)
 {
@@ -257,6 +264,15 @@ __device__ __forceinline__ float pair_u_ri(const KParams &p, float r2, float ri)
     const float ri2 = ri * ri, rpi2 = rpi * rpi;
     const float uu = p.c5f * (ri2 * ri2 * ri + rpi2 * rpi2 * rpi) + p.u0f;
     return r2 <= p.h2f ? uu : 0.0f;
+}
+
+__device__ __forceinline__ float pair_u_in(const KParams &p, float r2, float ri, bool keep)
+{
+    const float r = r2 * ri;
+    const float rpi = __builtin_amdgcn_rcpf(p.Lf - r);
+    const float ri2 = ri * ri, rpi2 = rpi * rpi;
+    const float uu = p.c5f * (ri2 * ri2 * ri + rpi2 * rpi2 * rpi) + p.u0f;
+    return (keep && r2 <= p.h2f) ? uu : 0.0f;
 }
 
 __device__ __forceinline__ float pair_v_ri(const KParams &p, float r2, float ri)

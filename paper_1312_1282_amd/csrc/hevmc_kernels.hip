@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "hevmc_device.hpp"
 #include "hevmc_internal.hpp"
@@ -44,6 +45,19 @@ __device__ __forceinline__ void walker_sync()
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     } else {
         __syncthreads();
+    }
+}
+
+// True on every thread of a walker if pred holds on any of them (the walker's
+// threads must all arrive; acts as walker_sync).
+template <int NT>
+__device__ __forceinline__ bool walker_any(bool pred)
+{
+    if constexpr (NT == 64) {
+        walker_sync<64>();
+        return __builtin_amdgcn_ballot_w64(pred) != 0;
+    } else {
+        return __syncthreads_or(pred ? 1 : 0) != 0;
     }
 }
 
@@ -214,10 +228,18 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
     double *ru = reinterpret_cast<double *>(smem_raw + rows_lds_offset(n, sizeof(T)));
     const int tid = walker_tid<NT>(), lane = tid & 63, wave = tid >> 6;
 
-    for (int i = tid; i < 3 * n; i += NT)
-        sx[i] = g[i];
+    bool bad = false;
+    for (int i = tid; i < 3 * n; i += NT) {
+        const T v = g[i];
+        sx[i] = v;
+        bad |= !isfinite((double)v);
+    }
     hevmc_walker_acc a = *accp;
     double u_run = a.u_run, v_run = a.v_run;
+    // a walker with a non-finite coordinate (whose pairs would silently drop
+    // out of every sum) leaves the launch with NaN running totals, which the
+    // caller detects
+    const bool bad_walker = walker_any<NT>(bad);
     int64_t n_acc = 0, n_try = 0, n_samp = 0, n_swm = 0;
     if constexpr (ROWS) {
         bool valid = false;
@@ -279,8 +301,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                         if (i < n) {
                             r2 = dist2(p, nx, ny, nz, sx[i], sy[i], sz[i]);
                             ri = inv_sqrt(r2);
-                            uu = pair_u_ri(p, r2, ri);
-                            uu = (i == s) ? T(0) : uu;
+                            uu = pair_u_in(p, r2, ri, i != s);
                         }
                         un_[jj] = uu;
                         r2n_[jj] = r2;
@@ -427,8 +448,8 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                 rg[i] = ru[i];
     }
     if (tid == 0) {
-        a.u_run = u_run;
-        a.v_run = v_run;
+        a.u_run = bad_walker ? __builtin_nan("") : u_run;
+        a.v_run = bad_walker ? __builtin_nan("") : v_run;
         a.n_samples += n_samp;
         a.n_sweeps_meas += n_swm;
         a.n_acc += n_acc;
@@ -484,7 +505,7 @@ __global__ __launch_bounds__(NT) void k_sweep_batch(BatchArgs b, const int32_t *
 // walkers of a workgroup share nothing but the compute unit; each has its own
 // LDS region of walker_lds bytes and never waits for the others.
 template <typename T, bool ROWS>
-__global__ __launch_bounds__(64 * kWalkersPerGroup) void k_sweep_wave(KParams p, T *__restrict__ coords,
+__global__ __launch_bounds__(64 * kWalkersPerGroup) __attribute__((amdgpu_waves_per_eu(2))) void k_sweep_wave(KParams p, T *__restrict__ coords,
                                                                       hevmc_walker_acc *__restrict__ accs,
                                                                       double *__restrict__ rows_hbm, int32_t W,
                                                                       uint32_t walker_lds, uint32_t sweep0,
@@ -502,7 +523,7 @@ __global__ __launch_bounds__(64 * kWalkersPerGroup) void k_sweep_wave(KParams p,
 }
 
 template <typename T, bool ROWS>
-__global__ __launch_bounds__(64 * kWalkersPerGroup) void k_sweep_batch_wave(
+__global__ __launch_bounds__(64 * kWalkersPerGroup) __attribute__((amdgpu_waves_per_eu(2))) void k_sweep_batch_wave(
     BatchArgs b, const int32_t *__restrict__ map, T *__restrict__ coords, hevmc_walker_acc *__restrict__ accs,
     double *__restrict__ rows_hbm, int32_t n_slots, uint32_t walker_lds, int32_t nsw)
 {
@@ -567,14 +588,17 @@ __global__ __launch_bounds__(NT) void k_init(KParams p, T *__restrict__ coords,
         for (int i = threadIdx.x; i < 3 * n; i += NT)
             sx[i] = g[i];
     }
-    __syncthreads();
+    bool bad = false;
+    for (int i = threadIdx.x; i < 3 * n; i += NT)
+        bad |= !isfinite((double)sx[i]);
+    bad = walker_any<NT>(bad);
     double el[6];
     local_energy_pass<T, NT>(p, sx, sx + n, sx + 2 * n, ebuf, el,
                              rows ? rows + (size_t)blockIdx.x * (size_t)n : nullptr);
     if (threadIdx.x == 0) {
         hevmc_walker_acc a = {};
-        a.u_run = el[5];
-        a.v_run = el[1];
+        a.u_run = bad ? __builtin_nan("") : el[5];
+        a.v_run = bad ? __builtin_nan("") : el[1];
         accs[blockIdx.x] = a;
     }
 }
@@ -798,7 +822,23 @@ static const void *sweep_fn(bool rows)
 }
 
 // Registers per thread of the sweep kernel a launch would use (0 if unknown).
+static int sweep_vgprs_query(bool fp32, int threads, bool rows);
+
 int sweep_vgprs(bool fp32, int threads, bool rows)
+{
+    // kernel attributes do not change: query each (precision, threads, variant) once
+    static std::atomic<int> cache[2][6][2];
+    static std::atomic<bool> have[2][6][2];
+    const int t = threads == 64 ? 0 : threads == 128 ? 1 : threads == 256 ? 2 : threads == 512 ? 3 : threads == 1024 ? 4 : 5;
+    if (have[fp32][t][rows].load(std::memory_order_acquire))
+        return cache[fp32][t][rows].load(std::memory_order_relaxed);
+    const int v = sweep_vgprs_query(fp32, threads, rows);
+    cache[fp32][t][rows].store(v, std::memory_order_relaxed);
+    have[fp32][t][rows].store(true, std::memory_order_release);
+    return v;
+}
+
+static int sweep_vgprs_query(bool fp32, int threads, bool rows)
 {
     const void *f = nullptr;
     switch (threads) {

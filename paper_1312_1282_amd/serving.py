@@ -52,6 +52,7 @@ class Request:
     result: np.ndarray = None
     slot0: int = None
     rejected: str = None
+    failed: str = None      # set when a walker's state turns non-finite
 
     def params(self, threads=0, variant=abi.VARIANT_AUTO):
         return abi.make_params(self.n, self.walkers, precision=self.precision, density=self.density, b=self.b,
@@ -81,23 +82,16 @@ def request_stream(count, rate=configs.SERVE_RATE, seed=0, seed_base=1000):
     return out
 
 
-class _Pool:
-    """Device-resident walker slots of one (N, precision) class."""
+class SlotList:
+    """First-fit free list of walker slots [0, capacity): a request takes one
+    contiguous range, so its walkers sit next to each other in the pool."""
 
-    def __init__(self, n, precision, capacity, torch):
-        self.n, self.precision, self.capacity = n, precision, capacity
-        shape = abi.make_params(n, capacity, precision=precision)
-        self.coords, self.acc = abi.alloc_state(shape)
-        self.rows = abi.alloc_rows(shape)
-        self.map_host = np.full((capacity, 2), -1, dtype=np.int32)
-        self.map = torch.full((capacity, 2), -1, dtype=torch.int32, device="cuda")
-        self.stream = torch.cuda.Stream()
-        self.active = []            # requests in this class
-        self.event = None           # completion of the launch in flight
-        self.in_flight = []         # requests advanced by that launch
-        self.free = [(0, capacity)]
+    def __init__(self, capacity):
+        self.capacity = capacity
+        self.free = [(0, capacity)]     # (start, length), sorted, coalesced
 
     def alloc(self, w):
+        """Start of a free range of w slots, or None."""
         for k, (a, length) in enumerate(self.free):
             if length >= w:
                 if length == w:
@@ -119,9 +113,29 @@ class _Pool:
         self.free = merged
 
 
+class _Pool:
+    """Device-resident walker slots of one (N, precision) class."""
+
+    def __init__(self, n, precision, capacity, torch):
+        self.n, self.precision, self.capacity = n, precision, capacity
+        shape = abi.make_params(n, capacity, precision=precision)
+        self.coords, self.acc = abi.alloc_state(shape)
+        self.rows = abi.alloc_rows(shape)
+        self.map_host = np.full((capacity, 2), -1, dtype=np.int32)
+        self.map = torch.full((capacity, 2), -1, dtype=torch.int32, device="cuda")
+        self.stream = torch.cuda.Stream()
+        # the buffers were filled on the allocating stream: order the pool's
+        # own stream after that, or a walker start could land before the fill
+        self.stream.wait_stream(torch.cuda.current_stream())
+        self.active = []            # requests in this class
+        self.event = None           # completion of the launch in flight
+        self.in_flight = []         # requests advanced by that launch
+        self.slots = SlotList(capacity)
+
+
 class Server:
     def __init__(self, target_se=configs.SERVE_TARGET_SE, equil=200, m=5, check_every=50, min_samples=20,
-                 quantum=10, lds_oversubscription=4.0, max_requests_per_class=abi.MAX_BATCH,
+                 quantum=None, lds_oversubscription=4.0, max_requests_per_class=abi.MAX_BATCH,
                  slots_per_class=8192):
         self.target_se = target_se
         self.equil = equil
@@ -160,7 +174,7 @@ class Server:
         lds_total, _ = self.footprint(req)
         if self.used_budget + lds_total > self.budget:
             return False
-        a = pool.alloc(req.walkers)
+        a = pool.slots.alloc(req.walkers)
         if a is None:
             return False
         req.slot0 = a
@@ -179,7 +193,7 @@ class Server:
         req.done = now
         req.result = acc_np
         pool.active.remove(req)
-        pool.release(req.slot0, req.walkers)
+        pool.slots.release(req.slot0, req.walkers)
         pool.map_host[req.slot0:req.slot0 + req.walkers] = -1
         self.used_budget -= self.footprint(req)[0]
 
@@ -189,6 +203,25 @@ class Server:
         e = (acc_np["sum_e"] + acc_np["c_e"]) / np.maximum(ns, 1) / req.n
         se = float(e.std(ddof=1) / np.sqrt(len(e))) if len(e) > 1 else float("inf")
         return se, float(e.mean()), bool(ns.min() >= self.min_samples and se <= self.target_se)
+
+    def quantum_for(self, n):
+        """Sweeps per launch of a class: about the same GPU time per launch for
+        every N (a small walker's sweep is short).  A function of N only, so a
+        request is split into the same launches alone and in any mix; the
+        equilibration length is a multiple of it."""
+        if self.quantum:
+            return self.quantum
+        q = 100 if n <= 128 else 50 if n <= 300 else 25 if n <= 600 else 10
+        while self.equil % q:
+            q //= 2
+        return max(q, 1)
+
+    def cadence(self, n):
+        """Measured sweeps between stop-rule checks: check_every, or the
+        quantum if that is longer (checks fall on launch boundaries)."""
+        q = self.quantum_for(n)
+        c = max(self.check_every, q)
+        return c if c % q == 0 else q * ((c + q - 1) // q)
 
     def _launch(self, pool, torch):
         reqs = list(pool.active)
@@ -205,26 +238,35 @@ class Server:
             pool.map_host[r.slot0:r.slot0 + r.walkers, 0] = k
         with torch.cuda.stream(pool.stream):
             pool.map.copy_(torch.from_numpy(pool.map_host.copy()).pin_memory(), non_blocking=True)
-            abi.sweep_batch(arr, pool.map, pool.coords, pool.acc, pool.rows, self.quantum, stream=pool.stream)
+            abi.sweep_batch(arr, pool.map, pool.coords, pool.acc, pool.rows, self.quantum_for(pool.n),
+                            stream=pool.stream)
             ev = torch.cuda.Event()
             ev.record(pool.stream)
         pool.event = ev
         pool.in_flight = reqs
         self.launches += 1
-        self.moves += sum(r.walkers * r.n for r in reqs) * self.quantum
+        self.moves += sum(r.walkers * r.n for r in reqs) * self.quantum_for(pool.n)
 
     def _finish_quantum(self, pool, now):
         """The launch of pool is complete: advance counters, run stop checks."""
         due = []
+        q, c = self.quantum_for(pool.n), self.cadence(pool.n)
         for r in pool.in_flight:
-            r.sweeps += self.quantum
+            r.sweeps += q
             meas = r.sweeps - self.equil
-            if meas > 0 and meas % self.check_every == 0:
+            if meas > 0 and meas % c == 0:
                 due.append(r)
         if due:
             acc_all = abi.acc_to_numpy(pool.acc)
             for r in due:
                 acc_np = acc_all[r.slot0:r.slot0 + r.walkers].copy()
+                bad = ~(np.isfinite(acc_np["u_run"]) & np.isfinite(acc_np["v_run"]) & np.isfinite(acc_np["sum_e"]))
+                if bad.any():
+                    r.failed = f"{int(bad.sum())} walker(s) with a non-finite running state"
+                    self._retire(pool, r, acc_np, now)
+                    if self.log:
+                        self.log(f"fail  r{r.rid}: {r.failed}")
+                    continue
                 r.se, r.energy, ok = self._check(r, acc_np)
                 r.checks = getattr(r, "checks", 0) + 1
                 if self.log and not ok and r.checks % 20 == 0:
@@ -293,7 +335,7 @@ def latency_summary(requests, censored_at=None):
     still running when the run was stopped at censored_at count with their
     elapsed time censored_at - arrival, a lower bound, so the percentiles are
     lower bounds too when any request is censored."""
-    served = [r for r in requests if r.rejected is None]
+    served = [r for r in requests if r.rejected is None and r.failed is None]
     lat, cens = [], 0
     for r in served:
         if r.done is not None:
@@ -301,12 +343,14 @@ def latency_summary(requests, censored_at=None):
         elif censored_at is not None:
             lat.append(censored_at - r.arrival)
             cens += 1
+    failed = sum(1 for r in requests if r.failed is not None)
     if not lat:
-        return {"completed": 0, "censored": cens}
+        return {"completed": 0, "censored": cens, "failed": failed}
     lat = np.array(lat)
     return {
         "completed": len(served) - cens,
         "censored": cens,
+        "failed": failed,
         "percentiles_are_lower_bounds": cens > 0,
         "p50_s": float(np.percentile(lat, 50)),
         "p99_s": float(np.percentile(lat, 99)),

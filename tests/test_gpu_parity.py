@@ -329,3 +329,64 @@ def test_ensemble_from_host_coordinates():
     with pytest.raises(abi.HevmcError):
         abi.Ensemble(p, init_xyz=bad)
     e.close()
+
+
+# ---------------------------------------------------------------------------
+# checkpoint / resume and failure reporting
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_checkpoint_through_host_resumes_bitwise(variant):
+    """Walker state copied to host memory (coordinates, accumulators, row sums)
+    and back into fresh device buffers continues exactly as if never stopped:
+    the random stream is keyed by the sweep index, so the sweep counter is the
+    only other state (restart as in Sec. 5.4)."""
+    n, W = 256, 6
+    p = gparams(n, W, seed=17, variant=variant)
+    x_ref, a_ref = _gpu_chain(p, [8, 6], 3, 2)
+    coords, acc = abi.alloc_state(p)
+    rows = abi.alloc_rows(p)
+    abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
+    abi.sweep(p, coords, acc, 0, 8, 3, 2, rows=rows)
+    torch.cuda.synchronize()
+    saved = (coords.cpu().numpy().copy(), acc.cpu().numpy().copy(), rows.cpu().numpy().copy())
+    del coords, acc, rows
+    c2 = torch.from_numpy(saved[0]).cuda()
+    a2 = torch.from_numpy(saved[1]).cuda()
+    r2 = torch.from_numpy(saved[2]).cuda()
+    abi.sweep(p, c2, a2, 8, 6, 3, 2, rows=r2)
+    torch.cuda.synchronize()
+    assert np.array_equal(c2.cpu().numpy(), x_ref)
+    assert abi.acc_to_numpy(a2).tobytes() == a_ref.tobytes()
+
+
+@pytest.mark.parametrize("threads", [64, 128])
+def test_non_finite_state_is_reported(threads):
+    """A configuration holding NaN gives non-finite running totals (its pairs
+    fail every cutoff test, so without a check they would drop out of the sums
+    unnoticed); the ensemble layer reports HEVMC_ESTATE when it synchronises,
+    and the stateless calls leave NaN totals on that walker only."""
+    n, W = 64, 2
+    s_ = osys(n)
+    xs = np.stack([grid_config(n, s_.L, seed=w) for w in range(W)])
+    xs[1, 0, 5] = np.nan
+    p = gparams(n, W, threads=threads)
+    c2, a2 = torch.from_numpy(xs).cuda(), torch.zeros((W, abi.ACC_BYTES), dtype=torch.uint8, device="cuda")
+    abi.init_walkers(p, c2, a2, fcc_start=False)
+    torch.cuda.synchronize()
+    a = abi.acc_to_numpy(a2)
+    assert np.isfinite(a["u_run"][0]) and np.isnan(a["u_run"][1]) and np.isnan(a["v_run"][1])
+    abi.sweep(p, c2, a2, 0, 2, 0, 1)
+    torch.cuda.synchronize()
+    a = abi.acc_to_numpy(a2)
+    assert np.isfinite(a["u_run"][0]) and np.isnan(a["u_run"][1]) and np.isnan(a["v_run"][1])
+    coords = torch.from_numpy(xs).cuda()
+    acc = torch.zeros((W, abi.ACC_BYTES), dtype=torch.uint8, device="cuda")
+    import ctypes as C
+    h = C.c_void_p()
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert abi.lib().hevmc_create_on(C.byref(p), C.c_void_p(coords.data_ptr()), C.c_void_p(acc.data_ptr()), st,
+                                     C.byref(h)) == 0
+    assert abi.lib().hevmc_run(h, 3, 0, 0) == 0
+    assert abi.lib().hevmc_sync(h) == -5
+    assert b"non-finite" in abi.lib().hevmc_last_error()
+    assert abi.lib().hevmc_destroy(h) == 0

@@ -14,12 +14,12 @@ def _req(rid, n, W, precision, density, b, seed):
                            seed=seed)
 
 
-@pytest.mark.parametrize("precision", [abi.FP64, abi.FP32])
-def test_batched_launch_equals_single_requests(precision):
+@pytest.mark.parametrize("n,precision", [(256, abi.FP64), (256, abi.FP32), (1100, abi.FP64), (2048, abi.FP64),
+                                         (2048, abi.FP32), (4000, abi.FP32)])
+def test_batched_launch_equals_single_requests(n, precision):
     """Three requests with the same N and precision but their own density, b
     and seed share slot pools with gaps; after three launches of 7 sweeps each
     (the first equilibration only) every request equals its own hevmc_sweep run."""
-    n = 256
     reqs = [_req(0, n, 5, precision, 0.0190, 2.6, 11), _req(1, n, 3, precision, 0.0220, 3.0, 12),
             _req(2, n, 4, precision, 0.0255, 3.3, 13)]
     slots, starts = 20, [1, 8, 14]
@@ -67,6 +67,7 @@ def test_server_result_same_alone_and_in_mix():
     mk = lambda: [_req(0, 108, 64, abi.FP64, 0.0200, 2.8, 21), _req(1, 108, 96, abi.FP64, 0.0240, 3.1, 22),
                   _req(2, 256, 64, abi.FP32, 0.0219, 2.9, 23), _req(3, 108, 80, abi.FP32, 0.0210, 3.0, 24)]
     kw = dict(target_se=4e-3, equil=20, check_every=10, min_samples=2, quantum=5)
+    assert serving.Server(quantum=None).quantum_for(108) == 100 and serving.Server(quantum=None).cadence(108) == 100
     mix = serving.Server(**kw).run(mk(), realtime=False)
     for r in mix:
         assert r.done is not None and r.rejected is None
@@ -84,14 +85,3 @@ def test_server_rejects_walkers_that_do_not_fit():
         [big, small], realtime=False)
     assert out[0].rejected and "ENOFIT" in out[0].rejected
     assert out[1].done is not None
-
-
-def test_request_stream_recipe():
-    reqs = serving.request_stream(200)
-    gaps = np.diff([0.0] + [r.arrival for r in reqs])
-    assert abs(gaps.mean() - 1 / configs.SERVE_RATE) < 0.2 / configs.SERVE_RATE
-    assert {r.n for r in reqs} == set(configs.SERVE_N)
-    assert all(64 <= r.walkers <= 512 for r in reqs)
-    assert all(configs.SERVE_RHO[0] <= r.density <= configs.SERVE_RHO[1] for r in reqs)
-    assert all(configs.SERVE_B[0] <= r.b <= configs.SERVE_B[1] for r in reqs)
-    assert {r.precision for r in reqs} == {abi.FP64, abi.FP32}
