@@ -1,7 +1,10 @@
 """Build libhevmc.so (HIP, gfx950) in-tree with hipcc.
 
 Packed FP32 instructions are switched off for all device code
-(-target-feature -packed-fp32-ops).
+(-target-feature -packed-fp32-ops).  Multiply-adds are fused only within one
+source expression (-ffp-contract=on), never across statements, so that every
+kernel that inlines a device function rounds it the same way: a walker's
+results are then bitwise the same in the single and the batched sweep.
 """
 import os
 import subprocess
@@ -17,7 +20,7 @@ ARCH = os.environ.get("HEVMC_OFFLOAD_ARCH", "gfx950")
 
 def hipcc_flags():
     return [
-        f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+        f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wall", "-Wno-unused-function",
         "-I", os.path.join(ROOT, "include"), "-I", CSRC,

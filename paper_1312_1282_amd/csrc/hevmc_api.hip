@@ -2,6 +2,7 @@
 // the host-buffer parity entry.  Declarations and contracts: include/hevmc.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -158,6 +159,7 @@ size_t lds_needed(const hevmc_params *p)
     return (size_t)3 * (size_t)p->n * (p->precision == HEVMC_FP32 ? sizeof(float) : sizeof(double));
 }
 
+// LDS of one walker of the row-sum sweep.
 size_t rows_lds_bytes(const hevmc_params *p)
 {
     const size_t tsz = p->precision == HEVMC_FP32 ? sizeof(float) : sizeof(double);
@@ -182,7 +184,12 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L)
     const bool wave_mode = threads == 64;
     // walkers per workgroup: one, or kWalkersPerGroup single-wave walkers
     const int per_group = wave_mode ? kWalkersPerGroup : 1;
-    const size_t stat = wave_mode ? 64 : static_lds(threads);
+    // static LDS per workgroup: the reservation below, or what the sweep
+    // kernels actually declare if that is more
+    const bool fp32 = p->precision == HEVMC_FP32;
+    const SweepAttrs attr_plain = sweep_attrs(fp32, threads, false), attr_rows = sweep_attrs(fp32, threads, true);
+    const size_t stat = std::max<size_t>(wave_mode ? 64 : static_lds(threads),
+                                         (size_t)std::max(attr_plain.static_lds, attr_rows.static_lds));
     const size_t max_dyn = d.lds_per_block > stat ? d.lds_per_block - stat : 0;
     const size_t need_plain = lds_needed(p);
     const size_t need_rows = rows_lds_bytes(p);
@@ -196,16 +203,15 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L)
         return fail(HEVMC_ENOFIT, "row-sum sweep needs N <= %d x threads and %zu B of LDS per walker",
                     kRowsPerLane, need_rows);
     const bool use_rows = p->variant == HEVMC_VARIANT_ROWS || (p->variant == HEVMC_VARIANT_AUTO && rows_ok);
-    const size_t walker_need = ((use_rows ? need_rows : need_plain) + align16) & ~align16;
-    const size_t need = walker_need * per_group;
-    size_t lds = need;
     // workgroups a compute unit can hold: by LDS, and by waves (4 SIMDs, register
     // file shared by the waves of a SIMD)
     const int waves_per_group = threads / 64 * per_group;
-    const int by_waves = 4 * waves_per_simd(sweep_vgprs(p->precision == HEVMC_FP32, threads, use_rows)) /
-                         waves_per_group;
+    const int by_waves = 4 * waves_per_simd((use_rows ? attr_rows : attr_plain).vgprs) / waves_per_group;
     const int groups = (p->n_walkers + per_group - 1) / per_group;
     const int per_cu = (groups + d.cus - 1) / d.cus;
+    const size_t walker_need = ((use_rows ? need_rows : need_plain) + align16) & ~align16;
+    const size_t need = walker_need * per_group;
+    size_t lds = need;
     for (int r = per_cu; r >= 1; --r) {
         if (per_cu % r != 0)
             continue;
@@ -288,7 +294,7 @@ extern "C" hevmc_status hevmc_footprint(const hevmc_params *p, size_t *lds_bytes
     if (st != HEVMC_OK)
         return st;
     if (lds_bytes_per_walker)
-        *lds_bytes_per_walker = L.rows ? rows_lds_bytes(p) : lds_needed(p);
+        *lds_bytes_per_walker = L.walker_lds;
     if (hbm_bytes)
         *hbm_bytes = (lds_needed(p) + sizeof(hevmc_walker_acc) + (size_t)p->n * sizeof(double)) *
                      (size_t)p->n_walkers;

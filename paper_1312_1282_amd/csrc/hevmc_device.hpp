@@ -327,6 +327,39 @@ __device__ __forceinline__ void pair_energy(const KParams &p, double r2, ETerms 
     e.lap = in ? fma(2.0, dur, d2u) : 0.0;
 }
 
+// The gradient and row terms of an ordered pair alone: u and u'/r, zero beyond
+// L/2 (the symmetric terms V and the Laplacian are formed once per unordered
+// pair by the caller).
+__device__ __forceinline__ void pair_grad_u(const KParams &p, double r2, double &u, double &dur)
+{
+    const double ri = rsq_nr(r2);
+    const double r = r2 * ri;
+    const double rpi = rcp_nr(p.L - r);
+    const double ri2 = ri * ri, rpi2 = rpi * rpi;
+    const double ri5 = ri2 * ri2 * ri, rpi5 = rpi2 * rpi2 * rpi;
+    const double ri6 = ri5 * ri, rpi6 = rpi5 * rpi;
+    const double uu = fma(p.c5, ri5 + rpi5, p.u0);
+    const double du = -5.0 * p.c5 * (ri6 - rpi6);
+    const bool in = r2 <= p.h2;
+    u = in ? uu : 0.0;
+    dur = in ? du * ri : 0.0;
+}
+
+__device__ __forceinline__ void pair_grad_u(const KParams &p, float r2, double &u, double &dur)
+{
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * ri;
+    const float rpi = __builtin_amdgcn_rcpf(p.Lf - r);
+    const float ri2 = ri * ri, rpi2 = rpi * rpi;
+    const float ri5 = ri2 * ri2 * ri, rpi5 = rpi2 * rpi2 * rpi;
+    const float ri6 = ri5 * ri, rpi6 = rpi5 * rpi;
+    const float uu = p.c5f * (ri5 + rpi5) + p.u0f;
+    const float du = -5.0f * p.c5f * (ri6 - rpi6);
+    const bool in = r2 <= p.h2f;
+    u = in ? (double)uu : 0.0;
+    dur = in ? (double)(du * ri) : 0.0;
+}
+
 __device__ __forceinline__ void pair_energy(const KParams &p, float r2, ETerms &e)
 {
     const float ri = __builtin_amdgcn_rsqf(r2);

@@ -60,8 +60,12 @@ hipError_t launch_move_delta(const Launch &L, const void *coords, const int32_t 
                              double *out);
 hipError_t launch_draw_moves(const Launch &L, uint32_t t, int32_t *s, double *xi, double *d);
 
-// Registers per thread of the sweep kernel for (precision, threads, variant);
-// 0 if unknown.
-int sweep_vgprs(bool fp32, int threads, bool rows);
+// Registers per thread and static LDS bytes of the sweep kernel for
+// (precision, threads, variant); zeros if unknown.
+struct SweepAttrs {
+    int vgprs;
+    int static_lds;
+};
+SweepAttrs sweep_attrs(bool fp32, int threads, bool rows);
 
 }  // namespace hevmc

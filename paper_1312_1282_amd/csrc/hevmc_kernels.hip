@@ -48,19 +48,6 @@ __device__ __forceinline__ void walker_sync()
     }
 }
 
-// True on every thread of a walker if pred holds on any of them (the walker's
-// threads must all arrive; acts as walker_sync).
-template <int NT>
-__device__ __forceinline__ bool walker_any(bool pred)
-{
-    if constexpr (NT == 64) {
-        walker_sync<64>();
-        return __builtin_amdgcn_ballot_w64(pred) != 0;
-    } else {
-        return __syncthreads_or(pred ? 1 : 0) != 0;
-    }
-}
-
 // Thread index within a walker's NT threads.
 template <int NT>
 __device__ __forceinline__ int walker_tid() { return (int)(threadIdx.x & (NT - 1)); }
@@ -93,45 +80,96 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *buf)
     __syncthreads();
 }
 
+// True on every thread of a walker if pred holds on any of them (the walker's
+// threads must all arrive; acts as walker_sync).  For NT > 64, buf as in
+// block_sum (the runtime's workgroup vote would take LDS of its own, beyond
+// the launch plan's budget).
+template <int NT>
+__device__ __forceinline__ bool walker_any(bool pred, double *buf)
+{
+    if constexpr (NT == 64) {
+        walker_sync<64>();
+        return __builtin_amdgcn_ballot_w64(pred) != 0;
+    } else {
+        double f[1] = {pred ? 1.0 : 0.0};
+        block_sum<NT, 1>(f, buf);
+        return f[0] > 0.0;
+    }
+}
+
 // Local energy of the walker in LDS (Sec. 2 local value of H): out =
-// (E_L, V, T_PB, T_JF, T_F, U).  Each lane owns atoms i = tid + j*NT and sums
-// over all j != i (every pair twice, no atomics).  If rows is not null, the
-// row sums sum_{j != i} u(r_ij) of the lane's atoms are stored there (LDS or
-// global memory).
+// (E_L, V, T_PB, T_JF, T_F, U).  Each lane owns atoms i = tid + c*NT and visits
+// every other atom once, as j = i + k (mod N) for k = 1 .. N-1, so no atomics
+// are needed.  The gradient of ln psi and the row sum of atom i need all N-1
+// partners, but V and the Laplacian terms are symmetric in the pair: they are
+// formed only for offsets k < N/2 (weight 2 for the Laplacian sum over atoms,
+// which counts every pair twice) and k = N/2 (each such pair is met from both
+// of its atoms: weight 1 and 1/2), halving the costliest pair terms.  If rows
+// is not null, the row sums sum_{j != i} u(r_ij) of the lane's atoms are
+// stored there (LDS or global memory).
 template <typename T, int NT>
 __device__ void local_energy_pass(const KParams &p, const T *sx, const T *sy, const T *sz, double *buf,
                                   double out[6], double *rows)
 {
     const int n = p.n;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};   // sum |G_i|^2, sum L_i, sum V_i, sum U_i
+    const int half = (n - 1) / 2;   // offsets 1 .. half: all pair terms
+    const bool mid = (n & 1) == 0;  // offset n/2: the antipodal pair, met twice
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};   // sum |G_i|^2, sum L_i, V, sum U_i
     for (int i = walker_tid<NT>(); i < n; i += NT) {
         const T xi = sx[i], yi = sy[i], zi = sz[i];
-        double gx = 0, gy = 0, gz = 0, li = 0, vi = 0, ui = 0;
-        for (int j = 0; j < n; ++j) {
+        double gx = 0, gy = 0, gz = 0, ui = 0;
+        double lh = 0, vh = 0;   // offsets below n/2
+        double lm = 0, vm = 0;   // offset n/2
+        int j = i;
+        for (int k = 1; k <= half; ++k) {
+            j = (j + 1 == n) ? 0 : j + 1;
             const T dx = min_image(xi - sx[j], p);
             const T dy = min_image(yi - sy[j], p);
             const T dz = min_image(zi - sz[j], p);
-            const T r2 = dx * dx + dy * dy + dz * dz;
             ETerms e;
-            pair_energy(p, r2, e);
-            const bool self = (j == i);
-            const double dur = self ? 0.0 : e.dur;
+            pair_energy(p, dx * dx + dy * dy + dz * dz, e);
+            gx += e.dur * (double)dx;
+            gy += e.dur * (double)dy;
+            gz += e.dur * (double)dz;
+            ui += e.u;
+            lh += e.lap;
+            vh += e.v;
+        }
+        if (mid) {
+            j = (j + 1 == n) ? 0 : j + 1;
+            const T dx = min_image(xi - sx[j], p);
+            const T dy = min_image(yi - sy[j], p);
+            const T dz = min_image(zi - sz[j], p);
+            ETerms e;
+            pair_energy(p, dx * dx + dy * dy + dz * dz, e);
+            gx += e.dur * (double)dx;
+            gy += e.dur * (double)dy;
+            gz += e.dur * (double)dz;
+            ui += e.u;
+            lm = e.lap;
+            vm = e.v;
+        }
+        for (int k = half + 1 + (mid ? 1 : 0); k < n; ++k) {
+            j = (j + 1 == n) ? 0 : j + 1;
+            const T dx = min_image(xi - sx[j], p);
+            const T dy = min_image(yi - sy[j], p);
+            const T dz = min_image(zi - sz[j], p);
+            double u, dur;
+            pair_grad_u(p, dx * dx + dy * dy + dz * dz, u, dur);
             gx += dur * (double)dx;
             gy += dur * (double)dy;
             gz += dur * (double)dz;
-            li += self ? 0.0 : e.lap;
-            vi += self ? 0.0 : e.v;
-            ui += self ? 0.0 : e.u;
+            ui += u;
         }
         acc[0] += gx * gx + gy * gy + gz * gz;
-        acc[1] += li;
-        acc[2] += vi;
+        acc[1] += fma(2.0, lh, lm);
+        acc[2] += fma(0.5, vm, vh);
         acc[3] += ui;
         if (rows)
             rows[i] = ui;
     }
     block_sum<NT, 4>(acc, buf);
-    const double V = 0.5 * acc[2], U = 0.5 * acc[3];
+    const double V = acc[2], U = 0.5 * acc[3];
     const double tpb = -p.kappa * (acc[1] + acc[0]);
     out[0] = V + tpb;
     out[1] = V;
@@ -239,7 +277,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
     // a walker with a non-finite coordinate (whose pairs would silently drop
     // out of every sum) leaves the launch with NaN running totals, which the
     // caller detects
-    const bool bad_walker = walker_any<NT>(bad);
+    const bool bad_walker = walker_any<NT>(bad, ebuf);
     int64_t n_acc = 0, n_try = 0, n_samp = 0, n_swm = 0;
     if constexpr (ROWS) {
         bool valid = false;
@@ -290,10 +328,10 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                 const T nz = (T)wrap_box((double)oz + dz, p.L, p.invL);
                 const bool owner = (tid == s % NT);
                 if constexpr (ROWS) {
-                    // forward half: u at the new position only; r^2 and 1/r are
-                    // kept for the potential if the move is accepted
+                    // forward half: u at the new position only; r^2 is kept for
+                    // the potential if the move is accepted
                     double su = 0.0;
-                    T un_[kRowsPerLane], r2n_[kRowsPerLane], rin_[kRowsPerLane];
+                    T un_[kRowsPerLane], r2n_[kRowsPerLane];
 #pragma unroll
                     for (int jj = 0; jj < kRowsPerLane; ++jj) {
                         const int i = tid + jj * NT;
@@ -305,7 +343,6 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                         }
                         un_[jj] = uu;
                         r2n_[jj] = r2;
-                        rin_[jj] = ri;
                         su += (double)uu;
                     }
                     const double w0 = wave_sum(su);
@@ -352,7 +389,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                                 const T rio = inv_sqrt(r2o);
                                 const T uo = pair_u_ri(p, r2o, rio);
                                 const T vo = pair_v_ri(p, r2o, rio);
-                                const T vn = pair_v_ri(p, r2n_[jj], rin_[jj]);
+                                const T vn = pair_v_ri(p, r2n_[jj], inv_sqrt(r2n_[jj]));
                                 const bool other = (i != s);
                                 const double dr = other ? (double)un_[jj] - (double)uo : 0.0;
                                 ru[i] += dr;
@@ -577,6 +614,9 @@ __global__ __launch_bounds__(NT) void k_init(KParams p, T *__restrict__ coords,
     const int n = p.n;
     T *g = coords + (size_t)blockIdx.x * 3 * (size_t)n;
     const uint32_t wid = p.wid_base + blockIdx.x;
+    // each thread checks the coordinates it stores itself (the others' stores
+    // are visible only after the vote's barrier)
+    bool bad = false;
     if (fcc) {
         for (int i = threadIdx.x; i < n; i += NT) {
             T x, y, z;
@@ -585,13 +625,13 @@ __global__ __launch_bounds__(NT) void k_init(KParams p, T *__restrict__ coords,
             g[i] = x; g[n + i] = y; g[2 * n + i] = z;
         }
     } else {
-        for (int i = threadIdx.x; i < 3 * n; i += NT)
-            sx[i] = g[i];
+        for (int i = threadIdx.x; i < 3 * n; i += NT) {
+            const T v = g[i];
+            sx[i] = v;
+            bad |= !isfinite((double)v);
+        }
     }
-    bool bad = false;
-    for (int i = threadIdx.x; i < 3 * n; i += NT)
-        bad |= !isfinite((double)sx[i]);
-    bad = walker_any<NT>(bad);
+    bad = walker_any<NT>(bad, ebuf);
     double el[6];
     local_energy_pass<T, NT>(p, sx, sx + n, sx + 2 * n, ebuf, el,
                              rows ? rows + (size_t)blockIdx.x * (size_t)n : nullptr);
@@ -821,24 +861,27 @@ static const void *sweep_fn(bool rows)
     return rows ? (const void *)k_sweep<T, NT, true> : (const void *)k_sweep<T, NT, false>;
 }
 
-// Registers per thread of the sweep kernel a launch would use (0 if unknown).
-static int sweep_vgprs_query(bool fp32, int threads, bool rows);
+// Registers per thread and static LDS of the sweep kernel a launch would use
+// (zeros if unknown).
+static SweepAttrs sweep_attrs_query(bool fp32, int threads, bool rows);
 
-int sweep_vgprs(bool fp32, int threads, bool rows)
+SweepAttrs sweep_attrs(bool fp32, int threads, bool rows)
 {
     // kernel attributes do not change: query each (precision, threads, variant) once
-    static std::atomic<int> cache[2][6][2];
+    static std::atomic<int> vgprs[2][6][2], lds[2][6][2];
     static std::atomic<bool> have[2][6][2];
     const int t = threads == 64 ? 0 : threads == 128 ? 1 : threads == 256 ? 2 : threads == 512 ? 3 : threads == 1024 ? 4 : 5;
     if (have[fp32][t][rows].load(std::memory_order_acquire))
-        return cache[fp32][t][rows].load(std::memory_order_relaxed);
-    const int v = sweep_vgprs_query(fp32, threads, rows);
-    cache[fp32][t][rows].store(v, std::memory_order_relaxed);
+        return SweepAttrs{vgprs[fp32][t][rows].load(std::memory_order_relaxed),
+                          lds[fp32][t][rows].load(std::memory_order_relaxed)};
+    const SweepAttrs a = sweep_attrs_query(fp32, threads, rows);
+    vgprs[fp32][t][rows].store(a.vgprs, std::memory_order_relaxed);
+    lds[fp32][t][rows].store(a.static_lds, std::memory_order_relaxed);
     have[fp32][t][rows].store(true, std::memory_order_release);
-    return v;
+    return a;
 }
 
-static int sweep_vgprs_query(bool fp32, int threads, bool rows)
+static SweepAttrs sweep_attrs_query(bool fp32, int threads, bool rows)
 {
     const void *f = nullptr;
     switch (threads) {
@@ -850,12 +893,12 @@ static int sweep_vgprs_query(bool fp32, int threads, bool rows)
     case 256: f = fp32 ? sweep_fn<float, 256>(rows) : sweep_fn<double, 256>(rows); break;
     case 512: f = fp32 ? sweep_fn<float, 512>(rows) : sweep_fn<double, 512>(rows); break;
     case 1024: f = fp32 ? sweep_fn<float, 1024>(rows) : sweep_fn<double, 1024>(rows); break;
-    default: return 0;
+    default: return SweepAttrs{0, 0};
     }
     hipFuncAttributes a;
     if (hipFuncGetAttributes(&a, f) != hipSuccess)
-        return 0;
-    return a.numRegs;
+        return SweepAttrs{0, 0};
+    return SweepAttrs{a.numRegs, (int)a.sharedSizeBytes};
 }
 
 hipError_t launch_sweep(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows, uint32_t sweep0,

@@ -14,6 +14,17 @@ def _req(rid, n, W, precision, density, b, seed):
                            seed=seed)
 
 
+def _acc_diff(a, b):
+    """The accumulator fields that differ, with their largest relative difference."""
+    out = []
+    for f in abi.ACC_FIELDS + abi.ACC_INT_FIELDS:
+        if not np.array_equal(a[f], b[f]):
+            d = np.abs(a[f] - b[f]) / np.maximum(np.abs(a[f]), 1e-300)
+            w = int(np.argmax(np.where(np.isnan(d), np.inf, d)))
+            out.append(f"{f}: {d.max():.2e} at walker {w} ({a[f][w]!r} vs {b[f][w]!r})")
+    return "; ".join(out)
+
+
 @pytest.mark.parametrize("n,precision", [(256, abi.FP64), (256, abi.FP32), (1100, abi.FP64), (2048, abi.FP64),
                                          (2048, abi.FP32), (4000, abi.FP32)])
 def test_batched_launch_equals_single_requests(n, precision):
@@ -55,7 +66,8 @@ def test_batched_launch_equals_single_requests(n, precision):
             abi.sweep(p, c1, a1, 7 * q, 7, 7, 2, rows=r1)
         torch.cuda.synchronize()
         assert np.array_equal(c1.cpu().numpy(), xb[a:a + r.walkers])
-        assert abi.acc_to_numpy(a1).tobytes() == ab[a:a + r.walkers].tobytes()
+        a1 = abi.acc_to_numpy(a1)
+        assert a1.tobytes() == ab[a:a + r.walkers].tobytes(), _acc_diff(a1, ab[a:a + r.walkers])
     # unused slots untouched
     assert np.all(ab["n_try"][[0, 6, 7, 11, 12, 13, 18, 19]] == 0)
 
