@@ -236,7 +236,8 @@ def main():
     value = moves_per_step * args.steps / wall
     samples_per_step = wl.walkers * (S // m if m > 0 else 0)
     acc_rate = float(a["n_acc"].sum() / max(a["n_try"].sum(), 1))
-    rows_variant = abi.plan_uses_rows(p)
+    plan = abi.plan_launch(p)
+    rows_variant = plan["variant"] == abi.VARIANT_ROWS
     if rows_variant:
         pair_flop = FLOP_ROWS_FORWARD + acc_rate * FLOP_ROWS_ACCEPT
     else:
@@ -278,8 +279,10 @@ def main():
             "step_sigma_A": wl.step_sigma,
             "sweeps_per_step": S,
             "energy_every": m,
-            "threads_per_walker": p.threads or None,
+            "threads_per_walker": plan["threads"],
             "variant": "rows" if rows_variant else "plain",
+            "spatial_order": bool(plan["spatial_order"]),
+            "walkers_per_cu": plan["walkers_per_cu"],
         },
         "roofline": {
             "bound": "alu",

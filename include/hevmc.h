@@ -111,6 +111,23 @@ typedef struct {
     int64_t n_try;           /* attempted moves in measured sweeps                        */
 } hevmc_walker_acc;
 
+/* How the library will run a sweep of p on the current device (the launch
+ * plan; no work is done).  All fields are outputs. */
+typedef struct {
+    int32_t threads;          /* threads per walker                                       */
+    int32_t variant;          /* HEVMC_VARIANT_PLAIN or HEVMC_VARIANT_ROWS                 */
+    int32_t spatial_order;    /* 1: atoms are re-sorted by cell (Morton order) in LDS at
+                                 every sweep, so a wavefront's atoms are neighbours in
+                                 space; results are the same up to summation order       */
+    int32_t walkers_per_cu;   /* walkers one compute unit holds at a time                 */
+    uint64_t lds_per_walker;  /* LDS bytes of one walker                                  */
+    uint64_t lds_per_group;   /* dynamic LDS bytes requested per workgroup                */
+} hevmc_plan;
+
+/* Fills *out with the launch plan of hevmc_sweep for p.  HEVMC_ENOFIT as
+ * hevmc_footprint. */
+hevmc_status hevmc_plan_launch(const hevmc_params *p, hevmc_plan *out);
+
 /* Box side L = cbrt(n / density) (A), as every kernel uses it. */
 hevmc_status hevmc_box(const hevmc_params *p, double *L_out);
 

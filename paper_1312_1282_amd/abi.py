@@ -76,8 +76,19 @@ class WalkerAcc(C.Structure):
 
 assert C.sizeof(WalkerAcc) == ACC_BYTES
 
+class Plan(C.Structure):
+    _fields_ = [
+        ("threads", C.c_int32),
+        ("variant", C.c_int32),
+        ("spatial_order", C.c_int32),
+        ("walkers_per_cu", C.c_int32),
+        ("lds_per_walker", C.c_uint64),
+        ("lds_per_group", C.c_uint64),
+    ]
+
+
 EXPORTS = [
-    "hevmc_box", "hevmc_footprint", "hevmc_init_walkers", "hevmc_sweep", "hevmc_local_energy",
+    "hevmc_plan_launch", "hevmc_box", "hevmc_footprint", "hevmc_init_walkers", "hevmc_sweep", "hevmc_local_energy",
     "hevmc_move_delta", "hevmc_draw_moves", "hevmc_sweep_batch", "hevmc_create", "hevmc_create_on", "hevmc_run",
     "hevmc_sync", "hevmc_get_acc", "hevmc_get_coords", "hevmc_get_sweep", "hevmc_destroy",
     "hevmc_eval_config", "hevmc_last_error",
@@ -97,6 +108,7 @@ def lib():
         vp = C.c_void_p
         st = C.c_int
         sig = {
+            "hevmc_plan_launch": [P, C.POINTER(Plan)],
             "hevmc_box": [P, C.POINTER(C.c_double)],
             "hevmc_footprint": [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)],
             "hevmc_init_walkers": [P, vp, vp, vp, C.c_int32, vp],
@@ -157,11 +169,16 @@ def footprint(p):
     return lds.value, hbm.value
 
 
+def plan_launch(p):
+    """The library's launch plan for a sweep of p, as a dict."""
+    out = Plan()
+    _check(lib().hevmc_plan_launch(C.byref(p), C.byref(out)))
+    return {f: getattr(out, f) for f, _ in Plan._fields_}
+
+
 def plan_uses_rows(p):
     """True if the library runs the row-sum variant of the sweep for p."""
-    lds, _ = footprint(p)
-    tsz = 4 if p.precision == FP32 else 8
-    return lds > 3 * p.n * tsz
+    return plan_launch(p)["variant"] == VARIANT_ROWS
 
 
 # ---- torch-facing helpers -------------------------------------------------

@@ -209,7 +209,24 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L)
     const int by_waves = 4 * waves_per_simd((use_rows ? attr_rows : attr_plain).vgprs) / waves_per_group;
     const int groups = (p->n_walkers + per_group - 1) / per_group;
     const int per_cu = (groups + d.cus - 1) / d.cus;
-    const size_t walker_need = ((use_rows ? need_rows : need_plain) + align16) & ~align16;
+    // spatial order of the atoms (a resort per sweep; it lets whole waves skip
+    // the short-range exponentials): used when it costs no workgroups per
+    // compute unit.  The choice depends on (N, precision, threads, variant)
+    // only, never on the launch's size, so a walker's results do not either.
+    const size_t base_need = ((use_rows ? need_rows : need_plain) + align16) & ~align16;
+    bool sorted = false;
+    if (!wave_mode && p->n <= kRowsPerLane * threads && p->n <= 65535) {
+        const size_t tsz = fp32 ? sizeof(float) : sizeof(double);
+        const size_t with_sort = (sorted_walker_lds(p->n, tsz, use_rows) + align16) & ~align16;
+        auto fit = [&](size_t bytes) {
+            const int g = bytes > max_dyn ? 0 : (int)(d.lds_per_cu / (bytes * per_group + stat));
+            return by_waves > 0 ? std::min(g, by_waves) : g;
+        };
+        sorted = fit(with_sort) > 0 && fit(with_sort) >= fit(base_need);
+    }
+    const size_t walker_need =
+        sorted ? (sorted_walker_lds(p->n, fp32 ? sizeof(float) : sizeof(double), use_rows) + align16) & ~align16
+               : base_need;
     const size_t need = walker_need * per_group;
     size_t lds = need;
     for (int r = per_cu; r >= 1; --r) {
@@ -225,6 +242,7 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L)
         break;
     }
     make_kparams(p, L.k);
+    L.k.sorted = sorted ? 1 : 0;
     L.p.n_walkers_grid = p->n_walkers;
     L.threads = threads;
     L.fp32 = p->precision == HEVMC_FP32;
@@ -259,6 +277,7 @@ void make_kparams(const hevmc_params *p, KParams &k)
     k.h2f = (float)(h * h);
     k.c5f = (float)k.c5;
     k.u0f = (float)k.u0;
+    k.sorted = 0;
 }
 
 hevmc_status launched(hipError_t e, const char *what) { return e == hipSuccess ? HEVMC_OK : hip_fail(e, what); }
@@ -284,6 +303,27 @@ extern "C" hevmc_status hevmc_box(const hevmc_params *p, double *L_out)
     if (!L_out)
         return fail(HEVMC_EINVAL, "L_out is NULL");
     *L_out = box_side(p);
+    return HEVMC_OK;
+}
+
+extern "C" hevmc_status hevmc_plan_launch(const hevmc_params *p, hevmc_plan *out)
+{
+    if (!out)
+        return fail(HEVMC_EINVAL, "out must not be NULL");
+    Launch L;
+    hevmc_status st = plan(p, nullptr, L);
+    if (st != HEVMC_OK)
+        return st;
+    DeviceLimits d;
+    if ((st = device_limits(d)) != HEVMC_OK)
+        return st;
+    const int per_group = L.threads == 64 ? kWalkersPerGroup : 1;
+    out->threads = L.threads;
+    out->variant = L.rows ? HEVMC_VARIANT_ROWS : HEVMC_VARIANT_PLAIN;
+    out->spatial_order = L.k.sorted;
+    out->walkers_per_cu = (int32_t)(d.lds_per_cu / (L.lds_bytes + static_lds(L.threads))) * per_group;
+    out->lds_per_walker = L.walker_lds;
+    out->lds_per_group = L.lds_bytes;
     return HEVMC_OK;
 }
 
@@ -375,6 +415,8 @@ extern "C" hevmc_status hevmc_sweep_batch(int32_t n_requests, const hevmc_reques
     hevmc_status st = plan(&shape, stream, L);
     if (st != HEVMC_OK)
         return st;
+    for (int r = 0; r < n_requests; ++r)
+        b.k[r].sorted = L.k.sorted;
     if (n_sweeps == 0)
         return HEVMC_OK;
     return launched(launch_sweep_batch(L, b, map, n_slots, coords, acc, rows, n_sweeps), "batched sweep launch");

@@ -26,6 +26,7 @@ struct KParams {
     double u0;           // -2 f(L/2): u(r) = f(r) + f(L-r) + u0 (Eq. (8), as read)
     double kappa;        // hbar^2 / 2m
     float Lf, invLf, h2f, c5f, u0f;
+    int32_t sorted;      // sweep keeps the atoms in LDS in spatial (Morton) order
 };
 
 // HFD-B(HE) pair potential (Aziz, McCourt, Wong 1987), the interaction named
@@ -46,6 +47,10 @@ constexpr double rm2 = rm * rm;
 constexpr double Drm = D * rm;        // D / x = Drm / r
 constexpr double beta_rm2 = beta / (rm * rm);   // -alpha x + beta x^2 = beta_rm2 r^2 - alpha_rm r
 constexpr double alpha_rm = alpha / rm;
+// The repulsive exponential is skipped where its exponent is below rep_min:
+// there eps A e^a < 2.7e-18 K, under half an ulp of V itself at the distance
+// where that happens (9.27 A, V = -0.016 K).
+constexpr double rep_min = -55.0;
 }  // namespace az
 
 // --------------------------------------------------------------------------
@@ -173,7 +178,10 @@ __device__ __forceinline__ void pair_uv(const KParams &p, double r2, double &u, 
     const double rpi = rcp_nr(p.L - r);
     const double ri2 = ri * ri, rpi2 = rpi * rpi;
     const double uu = fma(p.c5, fma(ri2 * ri2, ri, rpi2 * rpi2 * rpi), p.u0);
-    const double rep = az::A * exp_neg(fma(az::beta_rm2, r2, -(az::alpha_rm * r)));
+    const double ea = fma(az::beta_rm2, r2, -(az::alpha_rm * r));
+    double rep = 0.0;
+    if (ea > az::rep_min)
+        rep = az::A * exp_neg(ea);
     const double y = az::rm2 * ri2;                   // x^-2
     const double y2 = y * y;
     const double disp = y2 * y * fma(y, fma(y, az::C10, az::C8), az::C6);
@@ -218,7 +226,10 @@ __device__ __forceinline__ double pair_u_in(const KParams &p, double r2, double 
 __device__ __forceinline__ double pair_v_ri(const KParams &p, double r2, double ri)
 {
     const double r = r2 * ri;
-    const double rep = az::A * exp_neg(fma(az::beta_rm2, r2, -(az::alpha_rm * r)));
+    const double ea = fma(az::beta_rm2, r2, -(az::alpha_rm * r));
+    double rep = 0.0;
+    if (ea > az::rep_min)
+        rep = az::A * exp_neg(ea);
     const double y = az::rm2 * (ri * ri);
     const double y2 = y * y;
     const double disp = y2 * y * fma(y, fma(y, az::C10, az::C8), az::C6);
@@ -309,7 +320,10 @@ __device__ __forceinline__ void pair_energy(const KParams &p, double r2, ETerms 
     const double uu = fma(p.c5, ri5 + rpi5, p.u0);
     const double du = -5.0 * p.c5 * (ri6 - rpi6);
     const double d2u = 30.0 * p.c5 * fma(ri6, ri, rpi6 * rpi);
-    const double rep = az::A * exp_neg(fma(az::beta_rm2, r2, -(az::alpha_rm * r)));
+    const double ea = fma(az::beta_rm2, r2, -(az::alpha_rm * r));
+    double rep = 0.0;
+    if (ea > az::rep_min)
+        rep = az::A * exp_neg(ea);
     const double y = az::rm2 * ri2;
     const double y2 = y * y;
     const double disp = y2 * y * fma(y, fma(y, az::C10, az::C8), az::C6);

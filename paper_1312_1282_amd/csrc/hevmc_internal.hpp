@@ -23,6 +23,32 @@ __host__ __device__ constexpr size_t rows_lds_offset(int n, size_t tsize)
     return ((size_t)3 * (size_t)n * tsize + 15) & ~(size_t)15;
 }
 
+// Spatial order of a walker's atoms in LDS (sweeps with KParams::sorted):
+// sort keys (Morton code of the atom's cell << 16 | atom label), padded to a
+// power of two, then slot_of[label] (uint16).  They follow the coordinates, or
+// the row sums of the row-sum variant.
+constexpr int kSortCells = 16;   // cells per box side for the Morton code
+__host__ __device__ constexpr int sort_keys(int n)
+{
+    int k = 1;
+    while (k < n)
+        k <<= 1;
+    return k;
+}
+__host__ __device__ constexpr size_t sort_lds_offset(int n, size_t tsize, bool rows)
+{
+    return rows ? (rows_lds_offset(n, tsize) + (size_t)n * sizeof(double) + 15) & ~(size_t)15
+                : ((size_t)3 * (size_t)n * tsize + 15) & ~(size_t)15;
+}
+__host__ __device__ constexpr size_t slot_of_lds_offset(int n, size_t tsize, bool rows)
+{
+    return sort_lds_offset(n, tsize, rows) + (size_t)sort_keys(n) * sizeof(uint32_t);
+}
+__host__ __device__ constexpr size_t sorted_walker_lds(int n, size_t tsize, bool rows)
+{
+    return slot_of_lds_offset(n, tsize, rows) + (size_t)n * sizeof(uint16_t);
+}
+
 // Per-request constants of a batched sweep, passed by value in the kernel
 // arguments (at most HEVMC_MAX_BATCH requests per launch).
 struct BatchArgs {

@@ -247,6 +247,78 @@ __device__ void fcc_site(const KParams &p, uint32_t wid, int pidx, int nc, doubl
 }
 
 // --------------------------------------------------------------------------
+// Morton code of the cell (kSortCells per side) that holds a position in [0, L).
+template <typename T>
+__device__ __forceinline__ uint32_t morton_cell(const KParams &p, T x, T y, T z)
+{
+    const double s = (double)kSortCells * p.invL;
+    const uint32_t cx = (uint32_t)min(kSortCells - 1, max(0, (int)((double)x * s)));
+    const uint32_t cy = (uint32_t)min(kSortCells - 1, max(0, (int)((double)y * s)));
+    const uint32_t cz = (uint32_t)min(kSortCells - 1, max(0, (int)((double)z * s)));
+    uint32_t m = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        m |= (((cx >> b) & 1u) << (3 * b)) | (((cy >> b) & 1u) << (3 * b + 1)) | (((cz >> b) & 1u) << (3 * b + 2));
+    return m;
+}
+
+// Puts a walker's atoms in LDS into the spatial order of their cells' Morton
+// codes, ties by label: keys are rebuilt from the current positions, sorted by
+// a bitonic network (pk keys, a power of two) and the coordinates (and rows)
+// are permuted through registers.  The order depends only on the positions,
+// so a run gives the same bits however it is split into launches.  Requires
+// n <= 8 NT.  Walker-wide: every thread of the walker must call it.
+template <typename T, int NT, bool ROWS>
+__device__ void walker_resort(const KParams &p, T *sx, T *sy, T *sz, double *ru, uint32_t *key,
+                              uint16_t *slot_of)
+{
+    const int n = p.n, pk = sort_keys(n), tid = walker_tid<NT>();
+    walker_sync<NT>();
+    for (int q = tid; q < pk; q += NT)
+        key[q] = q < n ? (morton_cell(p, sx[q], sy[q], sz[q]) << 16) | (key[q] & 0xFFFFu) : 0xFFFFFFFFu;
+    walker_sync<NT>();
+    for (int k = 2; k <= pk; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < (pk >> 1); i += NT) {
+                const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1)), hi = lo + j;
+                const uint32_t a = key[lo], b = key[hi];
+                if ((a > b) == ((lo & k) == 0)) {
+                    key[lo] = b;
+                    key[hi] = a;
+                }
+            }
+            walker_sync<NT>();
+        }
+    }
+    T gx[kRowsPerLane], gy[kRowsPerLane], gz[kRowsPerLane];
+    double gr[kRowsPerLane];
+#pragma unroll
+    for (int c = 0; c < kRowsPerLane; ++c) {
+        const int q = tid + c * NT;
+        if (q < n) {
+            const int o = slot_of[key[q] & 0xFFFFu];
+            gx[c] = sx[o];
+            gy[c] = sy[o];
+            gz[c] = sz[o];
+            gr[c] = ROWS ? ru[o] : 0.0;
+        }
+    }
+    walker_sync<NT>();
+#pragma unroll
+    for (int c = 0; c < kRowsPerLane; ++c) {
+        const int q = tid + c * NT;
+        if (q < n) {
+            sx[q] = gx[c];
+            sy[q] = gy[c];
+            sz[q] = gz[c];
+            if (ROWS)
+                ru[q] = gr[c];
+            slot_of[key[q] & 0xFFFFu] = (uint16_t)q;
+        }
+    }
+    walker_sync<NT>();
+}
+
 // One walker's sweeps (the body of the sweep kernels).  Dynamic LDS: x, y, z
 // (T) and, for ROWS, the row sums (double) at rows_lds_offset(n, sizeof(T)).
 // g: the walker's coordinates [3][N]; accp: its accumulators; rg: its row sums
@@ -265,6 +337,16 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
     T *sy = sx + n, *sz = sy + n;
     double *ru = reinterpret_cast<double *>(smem_raw + rows_lds_offset(n, sizeof(T)));
     const int tid = walker_tid<NT>(), lane = tid & 63, wave = tid >> 6;
+    // spatial order (p.sorted): LDS slot q holds the atom labelled key[q] & 0xFFFF
+    const bool sorted = NT > 64 && p.sorted != 0;
+    uint32_t *key = reinterpret_cast<uint32_t *>(smem_raw + sort_lds_offset(n, sizeof(T), ROWS));
+    uint16_t *slot_of = reinterpret_cast<uint16_t *>(smem_raw + slot_of_lds_offset(n, sizeof(T), ROWS));
+    if (sorted) {
+        for (int q = tid; q < n; q += NT) {
+            key[q] = (uint32_t)q;
+            slot_of[q] = (uint16_t)q;
+        }
+    }
 
     bool bad = false;
     for (int i = tid; i < 3 * n; i += NT) {
@@ -306,11 +388,18 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
     for (int it = 0; it < nsw; ++it) {
         const uint32_t t = sweep0 + (uint32_t)it;
         const bool measured = t >= mstart;
+        if (sorted) {
+            walker_resort<T, NT, ROWS>(p, sx, sy, sz, ru, key, slot_of);
+            last_s = -1;
+        }
         for (int k0 = 0; k0 < n; k0 += 64) {
-            // lane l draws the random numbers of micro-step k0 + l
+            // lane l draws the random numbers of micro-step k0 + l; the atom's
+            // label becomes its LDS slot
             int bs;
             double bxi, bdx, bdy, bdz;
             draw_move(p, (uint32_t)(k0 + lane), t, wid, bs, bxi, bdx, bdy, bdz);
+            if (sorted)
+                bs = slot_of[bs];
             const int kend = min(64, n - k0);
             for (int j = 0; j < kend; ++j) {
                 const int k = k0 + j;
@@ -477,12 +566,23 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
         }
     }
     walker_sync<NT>();
-    for (int i = tid; i < 3 * n; i += NT)
-        g[i] = sx[i];
-    if constexpr (ROWS) {
-        if (rg)
-            for (int i = tid; i < n; i += NT)
-                rg[i] = ru[i];
+    if (sorted) {
+        for (int q = tid; q < n; q += NT) {
+            const int l = (int)(key[q] & 0xFFFFu);
+            g[l] = sx[q];
+            g[n + l] = sy[q];
+            g[2 * n + l] = sz[q];
+            if (ROWS && rg)
+                rg[l] = ru[q];
+        }
+    } else {
+        for (int i = tid; i < 3 * n; i += NT)
+            g[i] = sx[i];
+        if constexpr (ROWS) {
+            if (rg)
+                for (int i = tid; i < n; i += NT)
+                    rg[i] = ru[i];
+        }
     }
     if (tid == 0) {
         a.u_run = bad_walker ? __builtin_nan("") : u_run;

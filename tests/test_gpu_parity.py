@@ -257,6 +257,23 @@ def test_split_launches_bitwise_identical(variant, threads):
     assert a1.tobytes() == a2.tobytes()
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_lockstep_spatial_order_ragged_n(variant):
+    """N = 300 (the sort pads its 512 keys) with atoms re-sorted by cell every
+    sweep: the chain still follows the oracle move for move, and a split run is
+    bitwise the same as one launch."""
+    n, W = 300, 3
+    p = gparams(n, W, threads=128, seed=17, wbase=7, variant=variant)
+    assert abi.plan_launch(p)["spatial_order"] == 1
+    xg, ag = _gpu_chain(p, [4, 5], 3, 2)
+    s_ = osys(n, seed=17)
+    for w in range(W):
+        xo, ao = _oracle_chain(s_, 7 + w, 9, 3, 2)
+        _compare_walker(xg[w], ag[w], xo, ao)
+    x1, a1 = _gpu_chain(p, [9], 3, 2)
+    assert np.array_equal(x1, xg) and a1.tobytes() == ag.tobytes()
+
+
 def test_stale_rows_buffer_is_recomputed():
     """A rows buffer that disagrees with u_run is detected and rebuilt: the
     result equals a run that recomputes the rows at every launch."""
@@ -390,3 +407,18 @@ def test_non_finite_state_is_reported(threads):
     assert abi.lib().hevmc_sync(h) == -5
     assert b"non-finite" in abi.lib().hevmc_last_error()
     assert abi.lib().hevmc_destroy(h) == 0
+
+
+@pytest.mark.parametrize("wl,threads,variant,spatial", [
+    (configs.C2_N2048_FP64, 256, abi.VARIANT_ROWS, 1),
+    (configs.C3_N2048_FP32, 256, abi.VARIANT_ROWS, 1),
+    (configs.C5_N10976_FP32, 512, abi.VARIANT_PLAIN, 0),
+    (configs.C1_SMALL_FP64, 64, abi.VARIANT_ROWS, 0),
+])
+def test_launch_plans_of_the_workloads(wl, threads, variant, spatial):
+    """The plans the parity and bench runs rely on: row sums where they fit,
+    spatial order where it costs no residency, one wave per small walker."""
+    plan = abi.plan_launch(abi.params_for(wl))
+    assert (plan["threads"], plan["variant"], plan["spatial_order"]) == (threads, variant, spatial), plan
+    assert plan["walkers_per_cu"] >= 1 and plan["lds_per_group"] >= plan["lds_per_walker"]
+
