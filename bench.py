@@ -21,22 +21,19 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FLOPs per unit of work, counted from the formulas (add, mul = 1,
-# fused multiply-add = 2; sqrt, reciprocals, rounding and exp count zero, so
-# fractions of peak are lower bounds):
-#   distance of one pair (difference, minimum image, r^2)          17
-#   u given r^-1, (L-r)^-1                                          11
-#   V given r, r^-2 (exponent, dispersion series, damping, scale)   18
-# plain sweep, per pair term: u and V at the old and the new position and the
-#   two differences accumulated                          2 (17+11+18) + 4 = 96
-# row-sum sweep, per pair: forward half (distance, u, sum)           29
-#   plus, for an accepted move: old u and V, new V, row update, dV   86
-# local energy, per unordered pair: distance, u, u', u'', V, gradient and
-#   Laplacian terms for both atoms, V and U sums                     70
-FLOP_PLAIN_PAIR = 96
-FLOP_ROWS_FORWARD = 29
-FLOP_ROWS_ACCEPT = 86
-FLOP_ENERGY_PAIR = 70
+# Algorithmic work: every micro-update forms the Eq. (7) sums over its N-1 pair
+# terms.  A pair term is the nominal sequence of the method at the old and the
+# new position of the moved atom (per position: 3 differences, minimum image
+# (mul, round, fma) x 3, r^2, cutoff compare, r^-2 and r^-5, L - r, (L-r)^-5,
+# u, x, repulsive argument and scale, x^-2 and x^-6, the C6/C8/C10 series,
+# damping argument and select, V, cutoff selects: 43 operations of which 12
+# are fused multiply-adds = 55 FLOP) plus 4 accumulating adds:
+# 2 x 55 + 4 = 114 FLOP.  Square roots, reciprocals and exponentials count
+# zero, and the local-energy samples are not counted at all, so the fraction
+# of peak is a lower bound.  It is the same figure for every variant: the
+# row-sum sweep reaches the same sums with fewer operations, so for it this is
+# an effective rate.
+FLOP_PER_PAIR_TERM = 114
 PEAK = {"f64": 78.6, "f32": 157.3}   # MI355X vector TFLOP/s (published)
 
 
@@ -52,7 +49,8 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="override the workload's atoms per walker")
     ap.add_argument("--walkers", type=int, default=0, help="override the workload's walker count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=5)
+    ap.add_argument("--cpu-sweeps", type=int, default=40,
+                    help="sweeps per walker of the CPU oracle sample (about 10 s on 16 host cores at N=2048)")
     ap.add_argument("--serve", type=int, default=0, metavar="REQUESTS",
                     help="instead of the sweep throughput, serve this many requests of the Poisson request "
                          "stream (20/s) until each reaches 1 mK/atom and report p50/p99 time-to-1mK")
@@ -150,8 +148,8 @@ def calibrate_copy(mib):
 
 def cpu_baseline(wl, sweeps):
     """The oracle as it stands, one walker per host thread, `sweeps` sweeps of
-    each with one local-energy sample (the step's work mix), from the fcc
-    start."""
+    each with a local-energy sample every m sweeps (the step's work mix), from
+    the fcc start."""
     import numpy as np
 
     import oracle as O
@@ -164,7 +162,8 @@ def cpu_baseline(wl, sweeps):
     xyz = np.stack([O.fcc_start(s_, w) for w in range(W)])
     accs = (O.Walker * W)(*[O.walker_init(s_, xyz[w]) for w in range(W)])
     t0 = time.perf_counter()
-    O.run_walkers(s_, 0, xyz, accs, 0, sweeps, 0, sweeps, cores)
+    m = wl.m if wl.m > 0 else sweeps
+    O.run_walkers(s_, 0, xyz, accs, 0, sweeps, 0, m, cores)
     dt = time.perf_counter() - t0
     moves = W * wl.n * sweeps
     return {
@@ -172,8 +171,8 @@ def cpu_baseline(wl, sweeps):
         "unit": "moves/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": f"{W} walkers x {sweeps} sweeps of N={wl.n} (+1 local energy each), one walker per thread, "
-                  f"{dt:.1f} s wall",
+        "sample": f"{W} walkers x {sweeps} sweeps of N={wl.n} with a local energy every {m} sweeps, "
+                  f"one walker per thread, {dt:.1f} s wall",
     }
 
 
@@ -234,16 +233,11 @@ def main():
     a = abi.acc_to_numpy(acc)
     moves_per_step = wl.walkers * wl.n * S
     value = moves_per_step * args.steps / wall
-    samples_per_step = wl.walkers * (S // m if m > 0 else 0)
     acc_rate = float(a["n_acc"].sum() / max(a["n_try"].sum(), 1))
     plan = abi.plan_launch(p)
     rows_variant = plan["variant"] == abi.VARIANT_ROWS
-    if rows_variant:
-        pair_flop = FLOP_ROWS_FORWARD + acc_rate * FLOP_ROWS_ACCEPT
-    else:
-        pair_flop = FLOP_PLAIN_PAIR
-    flop_launch = (moves_per_step * (wl.n - 1) * pair_flop
-                   + samples_per_step * (wl.n * (wl.n - 1) // 2) * FLOP_ENERGY_PAIR)
+    pair_terms_launch = moves_per_step * (wl.n - 1)
+    flop_launch = pair_terms_launch * FLOP_PER_PAIR_TERM
     avg_s = float(launch_ms.mean()) * 1e-3
     achieved = flop_launch / avg_s / 1e12
 
@@ -295,6 +289,8 @@ def main():
             "kernel": "k_sweep",
             "launch_ms_avg": float(launch_ms.mean()),
             "flop_per_launch": flop_launch,
+            "flop_per_pair_term": FLOP_PER_PAIR_TERM,
+            "pair_terms_per_launch": pair_terms_launch,
         },
         "physics": physics,
     }
