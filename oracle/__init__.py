@@ -78,6 +78,8 @@ def lib():
         L.or_delta.argtypes = [sp, dp, C.c_int32, dp, dp, dp, dp, dp]
         L.or_local_energy.argtypes = [sp, dp, dp, dp, dp, dp]
         L.or_fcc_start.argtypes = [sp, C.c_uint32, dp]
+        u64p = C.POINTER(C.c_uint64)
+        L.or_pair_histogram.argtypes = [sp, dp, C.c_int32, u64p, u64p, C.c_double]
         L.or_walker_init.argtypes = [sp, dp, wp]
         L.or_run_walker.argtypes = [sp, C.c_uint32, dp, wp, C.c_uint32, C.c_int32, C.c_uint32,
                                     C.c_int32, dp, C.POINTER(C.c_int64)]
@@ -180,6 +182,18 @@ def local_energy(sys_, xyz, want_derivs=False):
         return out, scale.value, g, lp
     lib().or_local_energy(C.byref(sys_), _dp(x), _dp(out), C.byref(scale), None, None)
     return out, scale.value
+
+
+def pair_histogram(sys_, xyz, nb, rel_window=0.0):
+    """(counts[nb], edge[nb+1]) of unordered pair distances in nb equal bins
+    over [0, L/2]; edge[b] counts pairs within rel_window of bin edge b."""
+    x = _f64(xyz, (3, sys_.n))
+    counts = np.zeros(nb, dtype=np.uint64)
+    edge = np.zeros(nb + 1, dtype=np.uint64)
+    u64p = C.POINTER(C.c_uint64)
+    lib().or_pair_histogram(C.byref(sys_), _dp(x), int(nb), counts.ctypes.data_as(u64p),
+                            edge.ctypes.data_as(u64p), float(rel_window))
+    return counts, edge
 
 
 def fcc_start(sys_, w):

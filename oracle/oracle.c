@@ -274,6 +274,39 @@ void or_delta(const or_system *sys, const double *xyz, int32_t s, const double r
  * kinetic estimators, and Sec. 5.4 lists two kinetic estimates that must agree
  * statistically; these are taken to be T_PB and T_JF, with T_F as a third.
  * All three have the same expectation over |psi|^2.  E_L = V + T_PB. */
+/* Pair distribution histogram (Sec. 5.4: the host analysis accumulates the
+ * pair distribution function of the sampled configurations; Sec. 7 cuts every
+ * pair term at half the box).  Bins of equal width in r over [0, L/2]. */
+void or_pair_histogram(const or_system *sys, const double *xyz, int32_t nb, uint64_t *counts,
+                       uint64_t *edge, double rel_window)
+{
+    const int n = sys->n;
+    const double h = 0.5 * sys->L;
+    const double width = h / nb;
+    double d[3];
+    for (int b = 0; b < nb; ++b)
+        counts[b] = 0;
+    if (edge)
+        for (int b = 0; b <= nb; ++b)
+            edge[b] = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            const double r = pair_dist(sys, xyz, i, j, d);
+            const double x = r / width;
+            if (edge) {
+                const double e = floor(x + 0.5);
+                if (e <= nb && fabs(x - e) <= rel_window * (e > 1.0 ? e : 1.0))
+                    edge[(int)e] += 1;
+            }
+            if (r > h)
+                continue;
+            int b = (int)floor(x);
+            if (b >= nb)
+                b = nb - 1;
+            counts[b] += 1;
+        }
+}
+
 void or_local_energy(const or_system *sys, const double *xyz, double out[6], double *scale,
                      double *grad, double *lap)
 {

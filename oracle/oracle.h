@@ -91,6 +91,16 @@ void or_local_energy(const or_system *sys, const double *xyz, double out[6], dou
                      double *grad, double *lap);
 
 /* fcc start with deterministic Philox jitter for walker id w. */
+/* Pair distribution histogram of one configuration (the g(r) the paper's
+ * host analysis computes, Sec. 5.4 and Sec. 7): counts[b], b = 0..nb-1, is the
+ * number of unordered pairs whose minimum-image distance r lies in
+ * [b h/nb, (b+1) h/nb), h = L/2, with r = h itself in the last bin and pairs
+ * beyond h not counted.  edge[b] (may be NULL) counts the pairs whose r/(h/nb)
+ * lies within rel_window of the integer b (a bin edge; b = nb is the cutoff),
+ * where another rounding of r could put the pair in the neighbouring bin. */
+void or_pair_histogram(const or_system *sys, const double *xyz, int32_t nb, uint64_t *counts,
+                       uint64_t *edge, double rel_window);
+
 void or_fcc_start(const or_system *sys, uint32_t w, double *xyz);
 
 /* Fresh running state for a configuration: u_run, v_run from or_totals,
