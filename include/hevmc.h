@@ -170,6 +170,30 @@ hevmc_status hevmc_sweep(const hevmc_params *p, void *coords, hevmc_walker_acc *
                          uint32_t sweep0, int32_t n_sweeps, uint32_t measure_start,
                          int32_t energy_every, void *stream);
 
+/* ---- Pair distribution function g(r) ---------------------------------------- */
+
+#define HEVMC_MAX_GR_BINS 4096
+
+/* hevmc_sweep that also accumulates the pair distribution histogram, the
+ * g(r) of the paper's analysis of sampled configurations (Sec. 5.4, Sec. 7).
+ * At every local-energy sample, each unordered pair with minimum-image
+ * distance r <= L/2 adds 1 to gr[w][min(gr_bins - 1, floor(r gr_bins / (L/2)))]
+ * (gr: device [W][gr_bins] uint64, caller-owned, added to, never cleared).
+ * Normalisation: g(r_b) = counts_b / (samples * N/2 * (N/L^3) * shell volume of
+ * bin b).  gr = NULL is hevmc_sweep.  The sweep's results are bitwise the same
+ * with or without the histogram.  HEVMC_EINVAL for gr_bins outside
+ * [1, HEVMC_MAX_GR_BINS]; HEVMC_ENOFIT if the walker and the bins do not fit
+ * in one workgroup's LDS. */
+hevmc_status hevmc_sweep_gr(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
+                            uint64_t *gr, int32_t gr_bins, uint32_t sweep0, int32_t n_sweeps,
+                            uint32_t measure_start, int32_t energy_every, void *stream);
+
+/* The pair distribution histogram of each of the W configurations in coords
+ * (device [W][3][N] of the precision's type), binned as in hevmc_sweep_gr:
+ * counts (device [W][n_bins] uint64) is overwritten.  Asynchronous. */
+hevmc_status hevmc_pair_histogram(const hevmc_params *p, const void *coords, int32_t n_bins,
+                                  uint64_t *counts, void *stream);
+
 /* ---- Batched sweeps (serving: walkers of several requests in one launch) ---- */
 
 #define HEVMC_MAX_BATCH 16

@@ -88,7 +88,8 @@ class Plan(C.Structure):
 
 
 EXPORTS = [
-    "hevmc_plan_launch", "hevmc_box", "hevmc_footprint", "hevmc_init_walkers", "hevmc_sweep", "hevmc_local_energy",
+    "hevmc_plan_launch", "hevmc_box", "hevmc_footprint", "hevmc_init_walkers", "hevmc_sweep", "hevmc_sweep_gr",
+    "hevmc_pair_histogram", "hevmc_local_energy",
     "hevmc_move_delta", "hevmc_draw_moves", "hevmc_sweep_batch", "hevmc_create", "hevmc_create_on", "hevmc_run",
     "hevmc_sync", "hevmc_get_acc", "hevmc_get_coords", "hevmc_get_sweep", "hevmc_destroy",
     "hevmc_eval_config", "hevmc_last_error",
@@ -113,6 +114,8 @@ def lib():
             "hevmc_footprint": [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)],
             "hevmc_init_walkers": [P, vp, vp, vp, C.c_int32, vp],
             "hevmc_sweep": [P, vp, vp, vp, C.c_uint32, C.c_int32, C.c_uint32, C.c_int32, vp],
+            "hevmc_sweep_gr": [P, vp, vp, vp, vp, C.c_int32, C.c_uint32, C.c_int32, C.c_uint32, C.c_int32, vp],
+            "hevmc_pair_histogram": [P, vp, C.c_int32, vp, vp],
             "hevmc_local_energy": [P, vp, vp, vp],
             "hevmc_move_delta": [P, vp, vp, vp, vp, vp],
             "hevmc_draw_moves": [P, C.c_uint32, vp, vp, vp, vp],
@@ -238,10 +241,27 @@ def init_walkers(p, coords, acc, fcc_start=True, stream=None, rows=None):
                                     int(bool(fcc_start)), _stream(stream)))
 
 
-def sweep(p, coords, acc, sweep0, n_sweeps, measure_start=NO_MEASURE, energy_every=0, stream=None, rows=None):
-    _check(lib().hevmc_sweep(C.byref(p), _ptr(coords, coord_dtype(p), (p.n_walkers, 3, p.n), "coords"),
-                             _ptr(acc, None, (p.n_walkers, ACC_BYTES), "acc"), _rows_ptr(p, rows), int(sweep0),
-                             int(n_sweeps), int(measure_start), int(energy_every), _stream(stream)))
+def sweep(p, coords, acc, sweep0, n_sweeps, measure_start=NO_MEASURE, energy_every=0, stream=None, rows=None,
+          gr=None):
+    """hevmc_sweep, or hevmc_sweep_gr when gr (int64 [W][bins], device) is given."""
+    cp = _ptr(coords, coord_dtype(p), (p.n_walkers, 3, p.n), "coords")
+    ap = _ptr(acc, None, (p.n_walkers, ACC_BYTES), "acc")
+    if gr is None:
+        _check(lib().hevmc_sweep(C.byref(p), cp, ap, _rows_ptr(p, rows), int(sweep0), int(n_sweeps),
+                                 int(measure_start), int(energy_every), _stream(stream)))
+    else:
+        bins = int(gr.shape[-1])
+        gp = _ptr(gr, _torch().int64, (p.n_walkers, bins), "gr")
+        _check(lib().hevmc_sweep_gr(C.byref(p), cp, ap, _rows_ptr(p, rows), gp, bins, int(sweep0), int(n_sweeps),
+                                    int(measure_start), int(energy_every), _stream(stream)))
+
+
+def pair_histogram(p, coords, counts, stream=None):
+    """hevmc_pair_histogram: counts (int64 [W][bins], device) is overwritten."""
+    bins = int(counts.shape[-1])
+    _check(lib().hevmc_pair_histogram(C.byref(p), _ptr(coords, coord_dtype(p), (p.n_walkers, 3, p.n), "coords"),
+                                      bins, _ptr(counts, _torch().int64, (p.n_walkers, bins), "counts"),
+                                      _stream(stream)))
 
 
 def local_energy(p, coords, out, stream=None):

@@ -172,7 +172,7 @@ void make_kparams(const hevmc_params *p, KParams &k);
 // The request is padded so that each compute unit holds r walkers, r the
 // largest divisor of ceil(W / CUs) whose walkers fit in its LDS: the walkers
 // are then spread evenly over the chip, in equal rounds.
-hevmc_status plan(const hevmc_params *p, void *stream, Launch &L)
+hevmc_status plan(const hevmc_params *p, void *stream, Launch &L, int32_t gr_bins = 0)
 {
     hevmc_status st = check_params(p);
     if (st != HEVMC_OK)
@@ -224,9 +224,19 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L)
         };
         sorted = fit(with_sort) > 0 && fit(with_sort) >= fit(base_need);
     }
+    // the pair histogram (when the caller collects it) goes behind everything
+    // else; it never changes the plan's other choices, so a chain has the same
+    // bits with or without it
+    const size_t tsz_w = fp32 ? sizeof(float) : sizeof(double);
     const size_t walker_need =
-        sorted ? (sorted_walker_lds(p->n, fp32 ? sizeof(float) : sizeof(double), use_rows) + align16) & ~align16
-               : base_need;
+        gr_bins > 0
+            ? (hist_lds_offset(p->n, tsz_w, use_rows, sorted) + (size_t)gr_bins * sizeof(uint32_t) + align16) &
+                  ~align16
+        : sorted ? (sorted_walker_lds(p->n, tsz_w, use_rows) + align16) & ~align16
+                 : base_need;
+    if (walker_need * per_group > max_dyn)
+        return fail(HEVMC_ENOFIT, "walker of %d atoms with a %d-bin pair histogram needs %zu B of LDS; "
+                    "a workgroup can have %zu B", p->n, gr_bins, walker_need * per_group, max_dyn);
     const size_t need = walker_need * per_group;
     size_t lds = need;
     for (int r = per_cu; r >= 1; --r) {
@@ -243,6 +253,7 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L)
     }
     make_kparams(p, L.k);
     L.k.sorted = sorted ? 1 : 0;
+    L.k.gr_bins = gr_bins;
     L.p.n_walkers_grid = p->n_walkers;
     L.threads = threads;
     L.fp32 = p->precision == HEVMC_FP32;
@@ -278,6 +289,8 @@ void make_kparams(const hevmc_params *p, KParams &k)
     k.c5f = (float)k.c5;
     k.u0f = (float)k.u0;
     k.sorted = 0;
+    k.gr_bins = 0;
+    k.gr = nullptr;
 }
 
 hevmc_status launched(hipError_t e, const char *what) { return e == hipSuccess ? HEVMC_OK : hip_fail(e, what); }
@@ -359,10 +372,20 @@ extern "C" hevmc_status hevmc_sweep(const hevmc_params *p, void *coords, hevmc_w
                                     uint32_t sweep0, int32_t n_sweeps, uint32_t measure_start, int32_t energy_every,
                                     void *stream)
 {
+    return hevmc_sweep_gr(p, coords, acc, rows, nullptr, 0, sweep0, n_sweeps, measure_start, energy_every, stream);
+}
+
+extern "C" hevmc_status hevmc_sweep_gr(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
+                                       uint64_t *gr, int32_t gr_bins, uint32_t sweep0, int32_t n_sweeps,
+                                       uint32_t measure_start, int32_t energy_every, void *stream)
+{
+    if (gr && (gr_bins < 1 || gr_bins > HEVMC_MAX_GR_BINS))
+        return fail(HEVMC_EINVAL, "gr_bins = %d must be in [1, %d]", gr_bins, HEVMC_MAX_GR_BINS);
     Launch L;
-    hevmc_status st = plan(p, stream, L);
+    hevmc_status st = plan(p, stream, L, gr ? gr_bins : 0);
     if (st != HEVMC_OK)
         return st;
+    L.k.gr = gr;
     if (!coords || !acc)
         return fail(HEVMC_EINVAL, "coords and acc must be device pointers");
     if (n_sweeps < 0)
@@ -431,6 +454,28 @@ extern "C" hevmc_status hevmc_local_energy(const hevmc_params *p, const void *co
     if (!coords || !out)
         return fail(HEVMC_EINVAL, "coords and out must be device pointers");
     return launched(launch_local_energy(L, coords, out), "local-energy kernel launch");
+}
+
+extern "C" hevmc_status hevmc_pair_histogram(const hevmc_params *p, const void *coords, int32_t n_bins,
+                                            uint64_t *counts, void *stream)
+{
+    if (n_bins < 1 || n_bins > HEVMC_MAX_GR_BINS)
+        return fail(HEVMC_EINVAL, "n_bins = %d must be in [1, %d]", n_bins, HEVMC_MAX_GR_BINS);
+    Launch L;
+    hevmc_status st = plan(p, stream, L);
+    if (st != HEVMC_OK)
+        return st;
+    if (!coords || !counts)
+        return fail(HEVMC_EINVAL, "coords and counts must be device pointers");
+    const size_t tsz = p->precision == HEVMC_FP32 ? sizeof(float) : sizeof(double);
+    DeviceLimits d;
+    if ((st = device_limits(d)) != HEVMC_OK)
+        return st;
+    if (hist_lds_offset(p->n, tsz, false, false) + (size_t)n_bins * sizeof(uint32_t) + 1024 > d.lds_per_block)
+        return fail(HEVMC_ENOFIT, "a %d-atom configuration and %d bins do not fit in one workgroup's LDS", p->n,
+                    n_bins);
+    L.k.gr_bins = n_bins;
+    return launched(launch_pair_hist(L, coords, counts), "pair-histogram kernel launch");
 }
 
 extern "C" hevmc_status hevmc_move_delta(const hevmc_params *p, const void *coords, const int32_t *s,

@@ -27,6 +27,8 @@ struct KParams {
     double kappa;        // hbar^2 / 2m
     float Lf, invLf, h2f, c5f, u0f;
     int32_t sorted;      // sweep keeps the atoms in LDS in spatial (Morton) order
+    int32_t gr_bins;     // bins of the pair histogram accumulated at each sample (0: none)
+    uint64_t *gr;        // [W][gr_bins] histogram counts (device), or null
 };
 
 // HFD-B(HE) pair potential (Aziz, McCourt, Wong 1987), the interaction named
@@ -196,6 +198,10 @@ __device__ __forceinline__ void pair_uv(const KParams &p, double r2, double &u, 
     v = in ? vv : 0.0;
 }
 
+// Whether a pair at squared distance r2 is inside the (inclusive) cutoff.
+__device__ __forceinline__ bool pair_inside(const KParams &p, double r2) { return r2 <= p.h2; }
+__device__ __forceinline__ bool pair_inside(const KParams &p, float r2) { return r2 <= p.h2f; }
+
 // Reciprocal distance from r^2 in the pair's precision.
 __device__ __forceinline__ double inv_sqrt(double r2) { return rsq_nr(r2); }
 __device__ __forceinline__ float inv_sqrt(float r2) { return __builtin_amdgcn_rsqf(r2); }
@@ -307,6 +313,7 @@ __device__ __forceinline__ float pair_v_ri(const KParams &p, float r2, float ri)
 // u' = -5 c5 (r^-6 - (L-r)^-6), u'' = 30 c5 (r^-7 + (L-r)^-7).
 struct ETerms {
     double u, v, dur, lap;
+    double r;   // the pair distance (for the pair histogram)
 };
 
 __device__ __forceinline__ void pair_energy(const KParams &p, double r2, ETerms &e)
@@ -335,6 +342,7 @@ __device__ __forceinline__ void pair_energy(const KParams &p, double r2, ETerms 
     const double vv = az::eps * fma(-F, disp, rep);
     const double dur = du * ri;
     const bool in = r2 <= p.h2;
+    e.r = r;
     e.u = in ? uu : 0.0;
     e.v = in ? vv : 0.0;
     e.dur = in ? dur : 0.0;
@@ -397,6 +405,7 @@ __device__ __forceinline__ void pair_energy(const KParams &p, float r2, ETerms &
     const float vv = (float)az::eps * (rep - F * disp);
     const float dur = du * ri;
     const bool in = r2 <= p.h2f;
+    e.r = (double)r;
     e.u = in ? (double)uu : 0.0;
     e.v = in ? (double)vv : 0.0;
     e.dur = in ? (double)dur : 0.0;

@@ -49,6 +49,16 @@ __host__ __device__ constexpr size_t sorted_walker_lds(int n, size_t tsize, bool
     return slot_of_lds_offset(n, tsize, rows) + (size_t)n * sizeof(uint16_t);
 }
 
+// Byte offset of the pair histogram (uint32 [gr_bins]) in a walker's LDS,
+// behind everything else the sweep keeps there.
+__host__ __device__ constexpr size_t hist_lds_offset(int n, size_t tsize, bool rows, bool sorted)
+{
+    return ((sorted ? sorted_walker_lds(n, tsize, rows)
+                    : rows ? rows_lds_offset(n, tsize) + (size_t)n * sizeof(double) : (size_t)3 * n * tsize) +
+            15) &
+           ~(size_t)15;
+}
+
 // Per-request constants of a batched sweep, passed by value in the kernel
 // arguments (at most HEVMC_MAX_BATCH requests per launch).
 struct BatchArgs {
@@ -80,6 +90,7 @@ hipError_t launch_sweep(const Launch &L, void *coords, hevmc_walker_acc *acc, do
 hipError_t launch_sweep_batch(const Launch &L, const BatchArgs &b, const int32_t *map, int32_t n_slots,
                               void *coords, hevmc_walker_acc *acc, double *rows, int32_t nsw);
 hipError_t launch_local_energy(const Launch &L, const void *coords, double *out);
+hipError_t launch_pair_hist(const Launch &L, const void *coords, uint64_t *counts);
 hipError_t launch_init(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows, int fcc, int nc,
                        double a_lat);
 hipError_t launch_move_delta(const Launch &L, const void *coords, const int32_t *s, const double *d,

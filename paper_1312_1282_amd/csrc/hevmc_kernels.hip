@@ -106,11 +106,14 @@ __device__ __forceinline__ bool walker_any(bool pred, double *buf)
 // which counts every pair twice) and k = N/2 (each such pair is met from both
 // of its atoms: weight 1 and 1/2), halving the costliest pair terms.  If rows
 // is not null, the row sums sum_{j != i} u(r_ij) of the lane's atoms are
-// stored there (LDS or global memory).
-template <typename T, int NT>
+// stored there (LDS or global memory).  If hist is not null, every unordered
+// pair inside the cutoff is also counted in hist[min(nb - 1, floor(r nb / h))]
+// (the pair distribution histogram, LDS, integer adds in any order).
+template <typename T, int NT, bool HIST = false>
 __device__ void local_energy_pass(const KParams &p, const T *sx, const T *sy, const T *sz, double *buf,
-                                  double out[6], double *rows)
+                                  double out[6], double *rows, uint32_t *hist = nullptr, int nb = 0)
 {
+    const double bin_scale = (double)nb * 2.0 * p.invL;   // bins per Angstrom
     const int n = p.n;
     const int half = (n - 1) / 2;   // offsets 1 .. half: all pair terms
     const bool mid = (n & 1) == 0;  // offset n/2: the antipodal pair, met twice
@@ -120,12 +123,15 @@ __device__ void local_energy_pass(const KParams &p, const T *sx, const T *sy, co
         double gx = 0, gy = 0, gz = 0, ui = 0;
         double lh = 0, vh = 0;   // offsets below n/2
         double lm = 0, vm = 0;   // offset n/2
-        int j = i;
+        // partner j = i + k (mod n); its coordinates are loaded one step ahead
+        int j = (i + 1 == n) ? 0 : i + 1;
+        T xj = sx[j], yj = sy[j], zj = sz[j];
         for (int k = 1; k <= half; ++k) {
-            j = (j + 1 == n) ? 0 : j + 1;
-            const T dx = min_image(xi - sx[j], p);
-            const T dy = min_image(yi - sy[j], p);
-            const T dz = min_image(zi - sz[j], p);
+            const int jn = (j + 1 == n) ? 0 : j + 1;
+            const T xq = sx[jn], yq = sy[jn], zq = sz[jn];
+            const T dx = min_image(xi - xj, p);
+            const T dy = min_image(yi - yj, p);
+            const T dz = min_image(zi - zj, p);
             ETerms e;
             pair_energy(p, dx * dx + dy * dy + dz * dz, e);
             gx += e.dur * (double)dx;
@@ -134,12 +140,18 @@ __device__ void local_energy_pass(const KParams &p, const T *sx, const T *sy, co
             ui += e.u;
             lh += e.lap;
             vh += e.v;
+            if (HIST && pair_inside(p, dx * dx + dy * dy + dz * dz))
+                atomicAdd(&hist[min(nb - 1, (int)(e.r * bin_scale))], 1u);
+            j = jn;
+            xj = xq;
+            yj = yq;
+            zj = zq;
         }
         if (mid) {
-            j = (j + 1 == n) ? 0 : j + 1;
-            const T dx = min_image(xi - sx[j], p);
-            const T dy = min_image(yi - sy[j], p);
-            const T dz = min_image(zi - sz[j], p);
+            const int jn = (j + 1 == n) ? 0 : j + 1;
+            const T dx = min_image(xi - xj, p);
+            const T dy = min_image(yi - yj, p);
+            const T dz = min_image(zi - zj, p);
             ETerms e;
             pair_energy(p, dx * dx + dy * dy + dz * dz, e);
             gx += e.dur * (double)dx;
@@ -148,18 +160,30 @@ __device__ void local_energy_pass(const KParams &p, const T *sx, const T *sy, co
             ui += e.u;
             lm = e.lap;
             vm = e.v;
+            // the antipodal pair is met from both atoms: count it from the lower slot
+            if (HIST && i < j && pair_inside(p, dx * dx + dy * dy + dz * dz))
+                atomicAdd(&hist[min(nb - 1, (int)(e.r * bin_scale))], 1u);
+            j = jn;
+            xj = sx[j];
+            yj = sy[j];
+            zj = sz[j];
         }
         for (int k = half + 1 + (mid ? 1 : 0); k < n; ++k) {
-            j = (j + 1 == n) ? 0 : j + 1;
-            const T dx = min_image(xi - sx[j], p);
-            const T dy = min_image(yi - sy[j], p);
-            const T dz = min_image(zi - sz[j], p);
+            const int jn = (j + 1 == n) ? 0 : j + 1;
+            const T xq = sx[jn], yq = sy[jn], zq = sz[jn];
+            const T dx = min_image(xi - xj, p);
+            const T dy = min_image(yi - yj, p);
+            const T dz = min_image(zi - zj, p);
             double u, dur;
             pair_grad_u(p, dx * dx + dy * dy + dz * dz, u, dur);
             gx += dur * (double)dx;
             gy += dur * (double)dy;
             gz += dur * (double)dz;
             ui += u;
+            j = jn;
+            xj = xq;
+            yj = yq;
+            zj = zq;
         }
         acc[0] += gx * gx + gy * gy + gz * gz;
         acc[1] += fma(2.0, lh, lm);
@@ -322,11 +346,12 @@ __device__ void walker_resort(const KParams &p, T *sx, T *sy, T *sz, double *ru,
 // One walker's sweeps (the body of the sweep kernels).  Dynamic LDS: x, y, z
 // (T) and, for ROWS, the row sums (double) at rows_lds_offset(n, sizeof(T)).
 // g: the walker's coordinates [3][N]; accp: its accumulators; rg: its row sums
-// in HBM ([N] doubles) or null.  For NT = 64 the walker is one wave and red,
-// rsl, ebuf are not used.
-template <typename T, int NT, bool ROWS>
+// in HBM ([N] doubles) or null; grw: its pair histogram ([gr_bins], HIST
+// only).  For NT = 64 the walker is one wave and red, rsl, ebuf are not used.
+template <typename T, int NT, bool ROWS, bool HIST = false>
 __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *__restrict__ g,
                                              hevmc_walker_acc *__restrict__ accp, double *__restrict__ rg,
+                                             uint64_t *__restrict__ grw,
                                              uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t m,
                                              unsigned char *smem_raw, double (*red)[NT / 64][2], double *rsl,
                                              double *ebuf)
@@ -347,6 +372,10 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
             slot_of[q] = (uint16_t)q;
         }
     }
+    // pair histogram of the samples (grw: this walker's [gr_bins] counts)
+    const int nb = HIST ? p.gr_bins : 0;
+    uint32_t *hist =
+        HIST ? reinterpret_cast<uint32_t *>(smem_raw + hist_lds_offset(n, sizeof(T), ROWS, sorted)) : nullptr;
 
     bool bad = false;
     for (int i = tid; i < 3 * n; i += NT) {
@@ -544,9 +573,17 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
         }
         if (measured) {
             if (m > 0 && (t - mstart + 1) % (uint32_t)m == 0) {
+                if constexpr (HIST)
+                    for (int b = tid; b < nb; b += NT)
+                        hist[b] = 0u;
                 walker_sync<NT>();
                 double el[6];
-                local_energy_pass<T, NT>(p, sx, sy, sz, ebuf, el, ROWS ? ru : nullptr);
+                local_energy_pass<T, NT, HIST>(p, sx, sy, sz, ebuf, el, ROWS ? ru : nullptr, hist, nb);
+                if constexpr (HIST) {
+                    walker_sync<NT>();
+                    for (int b = tid; b < nb; b += NT)
+                        grw[b] += hist[b];
+                }
                 if (tid == 0) {
                     nsum(a.sum_e, a.c_e, el[0]);
                     nsum(a.sum_e2, a.c_e2, el[0] * el[0]);
@@ -595,8 +632,9 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
     }
 }
 
-// The sweep kernel (hevmc_sweep).  Grid: one workgroup of NT threads per walker.
-template <typename T, int NT, bool ROWS>
+// The sweep kernel (hevmc_sweep; HIST: hevmc_sweep_gr).  Grid: one workgroup of
+// NT threads per walker.
+template <typename T, int NT, bool ROWS, bool HIST>
 __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
                                               hevmc_walker_acc *__restrict__ accs,
                                               double *__restrict__ rows_hbm, uint32_t sweep0, int32_t nsw,
@@ -608,9 +646,10 @@ __global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
     __shared__ double ebuf[NT / 64 * 4];
     const int w = blockIdx.x;
     const size_t n = (size_t)p.n;
-    sweep_walker<T, NT, ROWS>(p, p.wid_base + (uint32_t)w, coords + (size_t)w * 3 * n, accs + w,
-                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, sweep0, nsw, mstart, m, smem_raw,
-                              red, rsl, ebuf);
+    sweep_walker<T, NT, ROWS, HIST>(p, p.wid_base + (uint32_t)w, coords + (size_t)w * 3 * n, accs + w,
+                                    rows_hbm ? rows_hbm + (size_t)w * n : nullptr,
+                                    HIST ? p.gr + (size_t)w * (size_t)p.gr_bins : nullptr, sweep0, nsw, mstart, m,
+                                    smem_raw, red, rsl, ebuf);
 }
 
 // The batched sweep kernel (hevmc_sweep_batch): walker slots of several
@@ -634,14 +673,14 @@ __global__ __launch_bounds__(NT) void k_sweep_batch(BatchArgs b, const int32_t *
     const uint32_t wid = (uint32_t)map[2 * w + 1];
     const size_t n = (size_t)b.k[r].n;
     sweep_walker<T, NT, ROWS>(b.k[r], wid, coords + (size_t)w * 3 * n, accs + w,
-                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, b.sweep0[r], nsw, b.mstart[r],
-                              b.m[r], smem_raw, red, rsl, ebuf);
+                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, nullptr, b.sweep0[r], nsw,
+                              b.mstart[r], b.m[r], smem_raw, red, rsl, ebuf);
 }
 
 // One wave per walker, kWalkersPerGroup walkers per workgroup (small N): the
 // walkers of a workgroup share nothing but the compute unit; each has its own
 // LDS region of walker_lds bytes and never waits for the others.
-template <typename T, bool ROWS>
+template <typename T, bool ROWS, bool HIST>
 __global__ __launch_bounds__(64 * kWalkersPerGroup) __attribute__((amdgpu_waves_per_eu(2))) void k_sweep_wave(KParams p, T *__restrict__ coords,
                                                                       hevmc_walker_acc *__restrict__ accs,
                                                                       double *__restrict__ rows_hbm, int32_t W,
@@ -654,9 +693,10 @@ __global__ __launch_bounds__(64 * kWalkersPerGroup) __attribute__((amdgpu_waves_
     if (w >= W)
         return;
     const size_t n = (size_t)p.n;
-    sweep_walker<T, 64, ROWS>(p, p.wid_base + (uint32_t)w, coords + (size_t)w * 3 * n, accs + w,
-                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, sweep0, nsw, mstart, m,
-                              smem_raw + (size_t)wv * walker_lds, nullptr, nullptr, nullptr);
+    sweep_walker<T, 64, ROWS, HIST>(p, p.wid_base + (uint32_t)w, coords + (size_t)w * 3 * n, accs + w,
+                                    rows_hbm ? rows_hbm + (size_t)w * n : nullptr,
+                                    HIST ? p.gr + (size_t)w * (size_t)p.gr_bins : nullptr, sweep0, nsw, mstart, m,
+                                    smem_raw + (size_t)wv * walker_lds, nullptr, nullptr, nullptr);
 }
 
 template <typename T, bool ROWS>
@@ -675,8 +715,34 @@ __global__ __launch_bounds__(64 * kWalkersPerGroup) __attribute__((amdgpu_waves_
     const uint32_t wid = (uint32_t)map[2 * w + 1];
     const size_t n = (size_t)b.k[r].n;
     sweep_walker<T, 64, ROWS>(b.k[r], wid, coords + (size_t)w * 3 * n, accs + w,
-                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, b.sweep0[r], nsw, b.mstart[r], b.m[r],
-                              smem_raw + (size_t)wv * walker_lds, nullptr, nullptr, nullptr);
+                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, nullptr, b.sweep0[r], nsw,
+                              b.mstart[r], b.m[r], smem_raw + (size_t)wv * walker_lds, nullptr, nullptr, nullptr);
+}
+
+// Pair distribution histograms of the W configurations (hevmc_pair_histogram):
+// counts[w][b] for p.gr_bins bins over [0, L/2], through the local-energy pass
+// that the sweep's samples use.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_pair_hist(KParams p, const T *__restrict__ coords,
+                                                  uint64_t *__restrict__ counts)
+{
+    constexpr int NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double ebuf[NW * 4];
+    T *sx = reinterpret_cast<T *>(smem_raw);
+    const int n = p.n, nb = p.gr_bins;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(smem_raw + hist_lds_offset(n, sizeof(T), false, false));
+    const T *g = coords + (size_t)blockIdx.x * 3 * (size_t)n;
+    for (int i = threadIdx.x; i < 3 * n; i += NT)
+        sx[i] = g[i];
+    for (int b = threadIdx.x; b < nb; b += NT)
+        hist[b] = 0u;
+    __syncthreads();
+    double el[6];
+    local_energy_pass<T, NT, true>(p, sx, sx + n, sx + 2 * n, ebuf, el, nullptr, hist, nb);
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += NT)
+        counts[(size_t)blockIdx.x * nb + b] = hist[b];
 }
 
 // Local energies of the W configurations (hevmc_local_energy).
@@ -809,47 +875,40 @@ static hipError_t allow_lds(K kern, size_t bytes)
     return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <typename T, int NT>
-static hipError_t launch_sweep_t(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows,
+template <typename T, int NT, bool ROWS, bool HIST>
+static hipError_t launch_sweep_v(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows,
                                  uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t m)
 {
     if constexpr (NT == 64) {
         const int groups = (L.p.n_walkers_grid + kWalkersPerGroup - 1) / kWalkersPerGroup;
-        const uint32_t wl = (uint32_t)L.walker_lds;
-        if (L.rows) {
-            auto kern = k_sweep_wave<T, true>;
-            hipError_t e = allow_lds(kern, L.lds_bytes);
-            if (e != hipSuccess)
-                return e;
-            hipLaunchKernelGGL(kern, dim3(groups), dim3(64 * kWalkersPerGroup), L.lds_bytes, L.stream, L.k,
-                               (T *)coords, acc, rows, L.p.n_walkers_grid, wl, sweep0, nsw, mstart, m);
-        } else {
-            auto kern = k_sweep_wave<T, false>;
-            hipError_t e = allow_lds(kern, L.lds_bytes);
-            if (e != hipSuccess)
-                return e;
-            hipLaunchKernelGGL(kern, dim3(groups), dim3(64 * kWalkersPerGroup), L.lds_bytes, L.stream, L.k,
-                               (T *)coords, acc, (double *)nullptr, L.p.n_walkers_grid, wl, sweep0, nsw, mstart,
-                               m);
-        }
-        return hipGetLastError();
-    }
-    if (L.rows) {
-        auto kern = k_sweep<T, NT, true>;
+        auto kern = k_sweep_wave<T, ROWS, HIST>;
         hipError_t e = allow_lds(kern, L.lds_bytes);
         if (e != hipSuccess)
             return e;
-        hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k, (T *)coords,
-                           acc, rows, sweep0, nsw, mstart, m);
+        hipLaunchKernelGGL(kern, dim3(groups), dim3(64 * kWalkersPerGroup), L.lds_bytes, L.stream, L.k,
+                           (T *)coords, acc, ROWS ? rows : (double *)nullptr, L.p.n_walkers_grid,
+                           (uint32_t)L.walker_lds, sweep0, nsw, mstart, m);
     } else {
-        auto kern = k_sweep<T, NT, false>;
+        auto kern = k_sweep<T, NT, ROWS, HIST>;
         hipError_t e = allow_lds(kern, L.lds_bytes);
         if (e != hipSuccess)
             return e;
         hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), L.lds_bytes, L.stream, L.k, (T *)coords,
-                           acc, (double *)nullptr, sweep0, nsw, mstart, m);
+                           acc, ROWS ? rows : (double *)nullptr, sweep0, nsw, mstart, m);
     }
     return hipGetLastError();
+}
+
+template <typename T, int NT>
+static hipError_t launch_sweep_t(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows,
+                                 uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t m)
+{
+    const bool hist = L.k.gr != nullptr && L.k.gr_bins > 0;
+    if (L.rows)
+        return hist ? launch_sweep_v<T, NT, true, true>(L, coords, acc, rows, sweep0, nsw, mstart, m)
+                    : launch_sweep_v<T, NT, true, false>(L, coords, acc, rows, sweep0, nsw, mstart, m);
+    return hist ? launch_sweep_v<T, NT, false, true>(L, coords, acc, rows, sweep0, nsw, mstart, m)
+                : launch_sweep_v<T, NT, false, false>(L, coords, acc, rows, sweep0, nsw, mstart, m);
 }
 
 template <typename T, int NT>
@@ -907,6 +966,18 @@ static hipError_t launch_energy_t(const Launch &L, const void *coords, double *o
 }
 
 template <typename T, int NT>
+static hipError_t launch_hist_t(const Launch &L, const void *coords, uint64_t *counts)
+{
+    auto kern = k_pair_hist<T, NT>;
+    const size_t bytes = hist_lds_offset(L.k.n, sizeof(T), false, false) + (size_t)L.k.gr_bins * sizeof(uint32_t);
+    hipError_t e = allow_lds(kern, bytes);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), bytes, L.stream, L.k, (const T *)coords, counts);
+    return hipGetLastError();
+}
+
+template <typename T, int NT>
 static hipError_t launch_init_t(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows, int fcc,
                                 int nc, double a_lat)
 {
@@ -958,7 +1029,7 @@ static hipError_t launch_delta_t(const Launch &L, const void *coords, const int3
 template <typename T, int NT>
 static const void *sweep_fn(bool rows)
 {
-    return rows ? (const void *)k_sweep<T, NT, true> : (const void *)k_sweep<T, NT, false>;
+    return rows ? (const void *)k_sweep<T, NT, true, false> : (const void *)k_sweep<T, NT, false, false>;
 }
 
 // Registers per thread and static LDS of the sweep kernel a launch would use
@@ -986,8 +1057,9 @@ static SweepAttrs sweep_attrs_query(bool fp32, int threads, bool rows)
     const void *f = nullptr;
     switch (threads) {
     case 64:
-        f = fp32 ? (rows ? (const void *)k_sweep_wave<float, true> : (const void *)k_sweep_wave<float, false>)
-                 : (rows ? (const void *)k_sweep_wave<double, true> : (const void *)k_sweep_wave<double, false>);
+        f = fp32 ? (rows ? (const void *)k_sweep_wave<float, true, false> : (const void *)k_sweep_wave<float, false, false>)
+                 : (rows ? (const void *)k_sweep_wave<double, true, false>
+                         : (const void *)k_sweep_wave<double, false, false>);
         break;
     case 128: f = fp32 ? sweep_fn<float, 128>(rows) : sweep_fn<double, 128>(rows); break;
     case 256: f = fp32 ? sweep_fn<float, 256>(rows) : sweep_fn<double, 256>(rows); break;
@@ -1016,6 +1088,11 @@ hipError_t launch_sweep_batch(const Launch &L, const BatchArgs &b, const int32_t
 hipError_t launch_local_energy(const Launch &L, const void *coords, double *out)
 {
     HEVMC_DISPATCH(launch_energy_t, coords, out);
+}
+
+hipError_t launch_pair_hist(const Launch &L, const void *coords, uint64_t *counts)
+{
+    HEVMC_DISPATCH(launch_hist_t, coords, counts);
 }
 
 hipError_t launch_init(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows, int fcc, int nc,

@@ -1,0 +1,150 @@
+"""GPU parity of the pair distribution histogram (g(r)) against the oracle.
+
+Bin counts are integers decided by a floating-point distance, so a pair whose
+r lies within rounding of a bin edge may land on either side: the oracle
+counts such pairs per edge (`edge[b]`, within a relative window fixed by the
+arithmetic: 1e-12 for FP64 distances from the same coordinates, 2e-6 for FP32
+distances, 1e-8 for chains that agree to 1e-9 A), and a bin may differ from
+the oracle by at most the ambiguous pairs at its two edges.  Everywhere else
+the counts are equal.
+"""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle as O
+from inputs import grid_config
+from paper_1312_1282_amd import abi, configs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RHO = configs.RHO_EQ
+B = configs.C1_SMALL_FP64.b
+STEP = configs.C1_SMALL_FP64.step_sigma
+
+
+def osys(n, seed=1, fp32=False):
+    return O.system(n, O.box_side(n, RHO, fp32=fp32), B, hbar2_over_m=configs.HBAR2_OVER_M, step_sigma=STEP,
+                    seed=seed)
+
+
+def _assert_counts(got, ref, edge):
+    got = np.asarray(got, dtype=np.int64)
+    ref = np.asarray(ref, dtype=np.int64)
+    slack = edge[:-1].astype(np.int64) + edge[1:].astype(np.int64)
+    bad = np.nonzero(np.abs(got - ref) > slack)[0]
+    assert bad.size == 0, (bad[:5], got[bad[:5]], ref[bad[:5]], slack[bad[:5]])
+    assert abs(int(got.sum()) - int(ref.sum())) <= int(edge[-1])
+
+
+@pytest.mark.parametrize("n,threads,precision,nb", [
+    (2, 64, abi.FP64, 10), (27, 128, abi.FP64, 20), (108, 64, abi.FP64, 50), (500, 256, abi.FP64, 100),
+    (2048, 256, abi.FP64, 200), (256, 128, abi.FP32, 64), (2048, 256, abi.FP32, 200),
+])
+def test_pair_histogram_matches_oracle(n, threads, precision, nb):
+    W = 3
+    fp32 = precision == abi.FP32
+    s_ = osys(n, fp32=fp32)
+    dt = np.float32 if fp32 else np.float64
+    xs = np.stack([grid_config(n, s_.L, seed=700 + n + w, dtype=dt) for w in range(W)])
+    p = abi.make_params(n, W, precision=precision, threads=threads, density=RHO, b=B)
+    counts = torch.zeros((W, nb), dtype=torch.int64, device="cuda")
+    abi.pair_histogram(p, torch.from_numpy(xs).cuda(), counts)
+    got = counts.cpu().numpy()
+    for w in range(W):
+        ref, edge = O.pair_histogram(s_, xs[w].astype(np.float64), nb, rel_window=2e-6 if fp32 else 1e-12)
+        _assert_counts(got[w], ref, edge)
+
+
+def test_pair_histogram_rejects_bad_bins():
+    p = abi.make_params(108, 1, density=RHO, b=B)
+    x = torch.zeros((1, 3, 108), dtype=torch.float64, device="cuda")
+    with pytest.raises(abi.HevmcError, match="EINVAL"):
+        abi.pair_histogram(p, x, torch.zeros((1, 0), dtype=torch.int64, device="cuda"))
+    with pytest.raises(abi.HevmcError, match="EINVAL"):
+        abi.pair_histogram(p, x, torch.zeros((1, 5000), dtype=torch.int64, device="cuda"))
+
+
+def _oracle_gr_chain(s_, w, n_sweeps, mstart, m, nb):
+    """Oracle chain from the fcc start with the histogram of every sample."""
+    x = O.fcc_start(s_, w)
+    a = O.walker_init(s_, x)
+    tot = np.zeros(nb, dtype=np.int64)
+    edges = np.zeros(nb + 1, dtype=np.int64)
+    t = 0
+    while t < n_sweeps:
+        # run to the next sample (or the end)
+        nxt = n_sweeps
+        if m > 0:
+            for u in range(max(t, mstart), n_sweeps):
+                if (u - mstart + 1) % m == 0:
+                    nxt = u + 1
+                    break
+        O.run_walker(s_, w, x, a, t, nxt - t, mstart, m, record_el=False)
+        if m > 0 and nxt - 1 >= mstart and (nxt - 1 - mstart + 1) % m == 0:
+            c, e = O.pair_histogram(s_, x, nb, rel_window=1e-8)
+            tot += c.astype(np.int64)
+            edges += e.astype(np.int64)
+        t = nxt
+    return x, a, tot, edges
+
+
+@pytest.mark.parametrize("n,threads,variant", [(256, 128, abi.VARIANT_ROWS), (256, 128, abi.VARIANT_PLAIN),
+                                               (108, 64, abi.VARIANT_ROWS)])
+def test_sweep_histogram_lockstep(n, threads, variant):
+    """Histograms accumulated at the samples of a chain equal the oracle's of its
+    own chain; the chain itself is bitwise the same with and without them."""
+    W, nb, mstart, m = 2, 64, 2, 3
+    p = abi.make_params(n, W, threads=threads, variant=variant, density=RHO, b=B, step_sigma=STEP, seed=5)
+    runs = {}
+    for with_gr in (False, True):
+        coords, acc = abi.alloc_state(p)
+        rows = abi.alloc_rows(p)
+        abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
+        gr = torch.zeros((W, nb), dtype=torch.int64, device="cuda") if with_gr else None
+        abi.sweep(p, coords, acc, 0, 5, mstart, m, rows=rows, gr=gr)
+        abi.sweep(p, coords, acc, 5, 6, mstart, m, rows=rows, gr=gr)
+        torch.cuda.synchronize()
+        runs[with_gr] = (coords.cpu().numpy(), abi.acc_to_numpy(acc), None if gr is None else gr.cpu().numpy())
+    assert np.array_equal(runs[False][0], runs[True][0])
+    assert runs[False][1].tobytes() == runs[True][1].tobytes()
+    got = runs[True][2]
+    s_ = osys(n, seed=5)
+    for w in range(W):
+        _, ao, ref, edge = _oracle_gr_chain(s_, w, 11, mstart, m, nb)
+        assert ao.n_samples == 3
+        _assert_counts(got[w], ref, edge)
+
+
+def test_sweep_histogram_n2048_w512_sampled_walkers():
+    """The benchmark's launch with a 200-bin histogram: walkers 0 and 511 are
+    replayed by the oracle; every walker counts the same number of pairs as
+    the ideal gas would within a few percent."""
+    wl = configs.C2_N2048_FP64
+    nb = 200
+    p = abi.params_for(wl)
+    coords, acc = abi.alloc_state(p)
+    rows = abi.alloc_rows(p)
+    abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
+    gr = torch.zeros((wl.walkers, nb), dtype=torch.int64, device="cuda")
+    abi.sweep(p, coords, acc, 0, 5, 0, 5, rows=rows, gr=gr)
+    torch.cuda.synchronize()
+    got = gr.cpu().numpy()
+    pairs = got.sum(axis=1)
+    expect = wl.n * (wl.n - 1) / 2 * np.pi / 6
+    assert np.all(np.abs(pairs / expect - 1.0) < 0.02)
+    s_ = osys(wl.n, seed=wl.seed)
+    res = {}
+
+    def work(w):
+        res[w] = _oracle_gr_chain(s_, w, 5, 0, 5, nb)
+
+    th = [threading.Thread(target=work, args=(w,)) for w in (0, 511)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for w in (0, 511):
+        _assert_counts(got[w], res[w][2], res[w][3])

@@ -103,3 +103,15 @@ def test_cutoff_pair_goes_to_last_bin_and_edges_are_flagged():
     x = np.array([[1.0, 7.5], [2.0, 2.0], [3.0, 3.0]])     # min image: r = 3.5
     counts, _ = O.pair_histogram(s, x, 5)
     assert counts.tolist() == [0, 0, 0, 1, 0]
+
+
+def test_pair_distribution_of_the_ideal_gas_is_one():
+    from paper_1312_1282_amd import observables
+    n, nb, reps = 64, 8, 300
+    s = osys(n)
+    tot = np.zeros(nb)
+    for k in range(reps):
+        tot += O.pair_histogram(s, uniform_config(n, s.L, seed=5000 + k), nb)[0]
+    r, g = observables.pair_distribution(tot, n, s.L, reps)
+    assert np.allclose(r, (np.arange(nb) + 0.5) * s.L / 2 / nb)
+    assert np.all(np.abs(g - 1.0) < 0.1) and abs(g[2:].mean() - 1.0) < 0.02
