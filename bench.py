@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="override the workload's atoms per walker")
     ap.add_argument("--walkers", type=int, default=0, help="override the workload's walker count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=40,
+    ap.add_argument("--cpu-sweeps", type=int, default=70,
                     help="sweeps per walker of the CPU oracle sample (about 10 s on 16 host cores at N=2048)")
     ap.add_argument("--serve", type=int, default=0, metavar="REQUESTS",
                     help="instead of the sweep throughput, serve this many requests of the Poisson request "
