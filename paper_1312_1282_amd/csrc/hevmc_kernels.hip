@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 
 #include "hevmc_device.hpp"
 #include "hevmc_internal.hpp"
@@ -410,6 +411,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
         walker_sync<NT>();
     }
 
+    const bool full = ROWS && n == kRowsPerLane * NT;   // every lane owns kRowsPerLane atoms
     int last_s = -1;          // atom accepted in the previous micro-update
     T lx = 0, ly = 0, lz = 0; // its new position (LDS copy not yet visible to all waves)
     double dv_pend = 0.0;     // ROWS: lane partial of dV of the last accepted move
@@ -450,19 +452,28 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                     // the potential if the move is accepted
                     double su = 0.0;
                     T un_[kRowsPerLane], r2n_[kRowsPerLane];
+                    // FULL: every lane owns kRowsPerLane atoms, so the unrolled
+                    // body has no per-lane branch and its loads issue up front
+                    auto forward = [&](auto full_c) {
+                        constexpr bool FULL = decltype(full_c)::value;
 #pragma unroll
-                    for (int jj = 0; jj < kRowsPerLane; ++jj) {
-                        const int i = tid + jj * NT;
-                        T uu = T(0), r2 = T(1), ri = T(1);
-                        if (i < n) {
-                            r2 = dist2(p, nx, ny, nz, sx[i], sy[i], sz[i]);
-                            ri = inv_sqrt(r2);
-                            uu = pair_u_in(p, r2, ri, i != s);
+                        for (int jj = 0; jj < kRowsPerLane; ++jj) {
+                            const int i = tid + jj * NT;
+                            T uu = T(0), r2 = T(1), ri = T(1);
+                            if (FULL || i < n) {
+                                r2 = dist2(p, nx, ny, nz, sx[i], sy[i], sz[i]);
+                                ri = inv_sqrt(r2);
+                                uu = pair_u_in(p, r2, ri, i != s);
+                            }
+                            un_[jj] = uu;
+                            r2n_[jj] = r2;
+                            su += (double)uu;
                         }
-                        un_[jj] = uu;
-                        r2n_[jj] = r2;
-                        su += (double)uu;
-                    }
+                    };
+                    if (full)
+                        forward(std::true_type{});
+                    else
+                        forward(std::false_type{});
                     const double w0 = wave_sum(su);
                     const double w1 = (last_s >= 0) ? wave_sum(dv_pend) : 0.0;
                     double SU = 0.0, DVP = 0.0, RS;
@@ -499,21 +510,28 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                         u_run += DU;
                         // old-position terms: update the rows, form dV
                         double dvl = 0.0;
+                        auto accept_pass = [&](auto full_c) {
+                            constexpr bool FULL = decltype(full_c)::value;
 #pragma unroll
-                        for (int jj = 0; jj < kRowsPerLane; ++jj) {
-                            const int i = tid + jj * NT;
-                            if (i < n) {
-                                const T r2o = dist2(p, ox, oy, oz, sx[i], sy[i], sz[i]);
-                                const T rio = inv_sqrt(r2o);
-                                const T uo = pair_u_ri(p, r2o, rio);
-                                const T vo = pair_v_ri(p, r2o, rio);
-                                const T vn = pair_v_ri(p, r2n_[jj], inv_sqrt(r2n_[jj]));
-                                const bool other = (i != s);
-                                const double dr = other ? (double)un_[jj] - (double)uo : 0.0;
-                                ru[i] += dr;
-                                dvl += other ? (double)vn - (double)vo : 0.0;
+                            for (int jj = 0; jj < kRowsPerLane; ++jj) {
+                                const int i = tid + jj * NT;
+                                if (FULL || i < n) {
+                                    const T r2o = dist2(p, ox, oy, oz, sx[i], sy[i], sz[i]);
+                                    const T rio = inv_sqrt(r2o);
+                                    const T uo = pair_u_ri(p, r2o, rio);
+                                    const T vo = pair_v_ri(p, r2o, rio);
+                                    const T vn = pair_v_ri(p, r2n_[jj], inv_sqrt(r2n_[jj]));
+                                    const bool other = (i != s);
+                                    const double dr = other ? (double)un_[jj] - (double)uo : 0.0;
+                                    ru[i] += dr;
+                                    dvl += other ? (double)vn - (double)vo : 0.0;
+                                }
                             }
-                        }
+                        };
+                        if (full)
+                            accept_pass(std::true_type{});
+                        else
+                            accept_pass(std::false_type{});
                         dv_pend = dvl;
                         if (owner) {
                             sx[s] = nx; sy[s] = ny; sz[s] = nz;
@@ -635,7 +653,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
 // The sweep kernel (hevmc_sweep; HIST: hevmc_sweep_gr).  Grid: one workgroup of
 // NT threads per walker.
 template <typename T, int NT, bool ROWS, bool HIST>
-__global__ __launch_bounds__(NT) void k_sweep(KParams p, T *__restrict__ coords,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_sweep(KParams p, T *__restrict__ coords,
                                               hevmc_walker_acc *__restrict__ accs,
                                               double *__restrict__ rows_hbm, uint32_t sweep0, int32_t nsw,
                                               uint32_t mstart, int32_t m)
