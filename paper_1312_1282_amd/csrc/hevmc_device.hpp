@@ -413,10 +413,12 @@ __device__ __forceinline__ void pair_energy(const KParams &p, float r2, ETerms &
 }
 
 // Metropolis decision of Eq. (5): accept if |psi'|^2/|psi|^2 = exp(2 dU) > xi,
-// xi in (0, 1); for dU >= 0 the ratio is >= 1 > xi.
-__device__ __forceinline__ bool metropolis_accept(double du, double xi)
+// xi in (0, 1), taken with the logarithm on the uniform: 2 dU > ln xi (the
+// same decision up to rounding; ln xi is formed ahead of the move, off the
+// decision's critical path).  For dU >= 0 the ratio is >= 1 > xi.
+__device__ __forceinline__ bool metropolis_accept_log(double du, double log_xi)
 {
-    return du >= 0.0 || exp_neg(2.0 * du) > xi;
+    return du >= 0.0 || 2.0 * du > log_xi;
 }
 
 // --------------------------------------------------------------------------

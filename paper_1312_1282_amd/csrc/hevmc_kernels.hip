@@ -429,13 +429,14 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
             int bs;
             double bxi, bdx, bdy, bdz;
             draw_move(p, (uint32_t)(k0 + lane), t, wid, bs, bxi, bdx, bdy, bdz);
+            const double blx = log(bxi);   // ln xi of micro-step k0 + lane
             if (sorted)
                 bs = slot_of[bs];
             const int kend = min(64, n - k0);
             for (int j = 0; j < kend; ++j) {
                 const int k = k0 + j;
                 const int s = readlane_i(bs, j);
-                const double xi = lane_value(bxi, j);
+                const double lxi = lane_value(blx, j);
                 const double dx = lane_value(bdx, j), dy = lane_value(bdy, j), dz = lane_value(bdz, j);
                 T ox, oy, oz;
                 if (s == last_s) {
@@ -501,7 +502,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                     v_run += DVP;
                     dv_pend = 0.0;
                     const double DU = SU - RS;
-                    const bool accept = metropolis_accept(DU, xi);
+                    const bool accept = metropolis_accept_log(DU, lxi);
                     if (measured) {
                         n_try += 1;
                         n_acc += accept ? 1 : 0;
@@ -563,7 +564,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                             DV += red[k & 1][q][1];
                         }
                     }
-                    const bool accept = metropolis_accept(DU, xi);
+                    const bool accept = metropolis_accept_log(DU, lxi);
                     if (measured) {
                         n_try += 1;
                         n_acc += accept ? 1 : 0;
