@@ -127,6 +127,7 @@ __device__ void local_energy_pass(const KParams &p, const T *sx, const T *sy, co
         // partner j = i + k (mod n); its coordinates are loaded one step ahead
         int j = (i + 1 == n) ? 0 : i + 1;
         T xj = sx[j], yj = sy[j], zj = sz[j];
+#pragma unroll 2
         for (int k = 1; k <= half; ++k) {
             const int jn = (j + 1 == n) ? 0 : j + 1;
             const T xq = sx[jn], yq = sy[jn], zq = sz[jn];
@@ -169,6 +170,7 @@ __device__ void local_energy_pass(const KParams &p, const T *sx, const T *sy, co
             yj = sy[j];
             zj = sz[j];
         }
+#pragma unroll 2
         for (int k = half + 1 + (mid ? 1 : 0); k < n; ++k) {
             const int jn = (j + 1 == n) ? 0 : j + 1;
             const T xq = sx[jn], yq = sy[jn], zq = sz[jn];

@@ -103,3 +103,11 @@ def test_request_stream_recipe():
     assert {r.precision for r in reqs} == {abi.FP64, abi.FP32}
     assert [r.seed for r in reqs] == list(range(1000, 1200))
     assert serving.request_stream(5)[3].arrival == serving.request_stream(5)[3].arrival
+
+
+def test_class_threads_depend_on_n_only():
+    srv = serving.Server()
+    assert [srv.threads_for(n) for n in configs.SERVE_N] == [128, 256, 256, 256, 0, 0]
+    assert serving.Server(latency_threads=False).threads_for(108) == 0
+    r = serving.Request(rid=0, arrival=0.0, n=500, walkers=64, precision=0, density=0.02, b=2.9, seed=3)
+    assert srv.params(r).threads == 256 and srv.params(r).n_walkers == 64
