@@ -194,6 +194,24 @@ hevmc_status hevmc_sweep_gr(const hevmc_params *p, void *coords, hevmc_walker_ac
 hevmc_status hevmc_pair_histogram(const hevmc_params *p, const void *coords, int32_t n_bins,
                                   uint64_t *counts, void *stream);
 
+/* ---- Per-sample records (correlated sampling over b) ---------------------- */
+
+/* hevmc_sweep that also writes, at every local-energy sample, the record
+ * (E_L, V, T_PB, T_JF, T_F, U) of the sampled configuration (the quantities of
+ * hevmc_local_energy) to trace[w][s][0..5], s the sample's index among all of
+ * walker w's samples (its n_samples before the sample), for s < trace_cap;
+ * later samples are counted in the accumulators but not recorded.
+ * trace: device [W][trace_cap][6] doubles, caller-owned.
+ * Because f of Eq. (9) scales as b^5, u for another b' is (b'/b)^5 u, and so
+ * are ln psi, its gradient and its Laplacian: each record gives E_L and the
+ * reweighting factor exp(2 (U_b' - U_b)) at any b' (Sec. 2 variational
+ * optimisation), see the host helper observables.reweight_b.  The sweep's
+ * results are bitwise the same with or without the trace.  HEVMC_EINVAL for
+ * trace_cap < 1. */
+hevmc_status hevmc_sweep_trace(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
+                               double *trace, int32_t trace_cap, uint32_t sweep0, int32_t n_sweeps,
+                               uint32_t measure_start, int32_t energy_every, void *stream);
+
 /* ---- Batched sweeps (serving: walkers of several requests in one launch) ---- */
 
 #define HEVMC_MAX_BATCH 16

@@ -291,6 +291,8 @@ void make_kparams(const hevmc_params *p, KParams &k)
     k.sorted = 0;
     k.gr_bins = 0;
     k.gr = nullptr;
+    k.trace = nullptr;
+    k.trace_cap = 0;
 }
 
 hevmc_status launched(hipError_t e, const char *what) { return e == hipSuccess ? HEVMC_OK : hip_fail(e, what); }
@@ -368,24 +370,22 @@ extern "C" hevmc_status hevmc_init_walkers(const hevmc_params *p, void *coords, 
     return launched(launch_init(L, coords, acc, rows, fcc_start ? 1 : 0, nc, L.k.L / nc), "init kernel launch");
 }
 
-extern "C" hevmc_status hevmc_sweep(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
-                                    uint32_t sweep0, int32_t n_sweeps, uint32_t measure_start, int32_t energy_every,
-                                    void *stream)
-{
-    return hevmc_sweep_gr(p, coords, acc, rows, nullptr, 0, sweep0, n_sweeps, measure_start, energy_every, stream);
-}
-
-extern "C" hevmc_status hevmc_sweep_gr(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
-                                       uint64_t *gr, int32_t gr_bins, uint32_t sweep0, int32_t n_sweeps,
-                                       uint32_t measure_start, int32_t energy_every, void *stream)
+// The sweep with its optional outputs: pair histogram and per-sample trace.
+static hevmc_status sweep_with(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
+                               uint64_t *gr, int32_t gr_bins, double *trace, int32_t trace_cap, uint32_t sweep0,
+                               int32_t n_sweeps, uint32_t measure_start, int32_t energy_every, void *stream)
 {
     if (gr && (gr_bins < 1 || gr_bins > HEVMC_MAX_GR_BINS))
         return fail(HEVMC_EINVAL, "gr_bins = %d must be in [1, %d]", gr_bins, HEVMC_MAX_GR_BINS);
+    if (trace && trace_cap < 1)
+        return fail(HEVMC_EINVAL, "trace_cap = %d must be >= 1", trace_cap);
     Launch L;
     hevmc_status st = plan(p, stream, L, gr ? gr_bins : 0);
     if (st != HEVMC_OK)
         return st;
     L.k.gr = gr;
+    L.k.trace = trace;
+    L.k.trace_cap = trace ? trace_cap : 0;
     if (!coords || !acc)
         return fail(HEVMC_EINVAL, "coords and acc must be device pointers");
     if (n_sweeps < 0)
@@ -398,6 +398,30 @@ extern "C" hevmc_status hevmc_sweep_gr(const hevmc_params *p, void *coords, hevm
         return HEVMC_OK;
     return launched(launch_sweep(L, coords, acc, rows, sweep0, n_sweeps, measure_start, energy_every),
                     "sweep kernel launch");
+}
+
+extern "C" hevmc_status hevmc_sweep(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
+                                    uint32_t sweep0, int32_t n_sweeps, uint32_t measure_start, int32_t energy_every,
+                                    void *stream)
+{
+    return sweep_with(p, coords, acc, rows, nullptr, 0, nullptr, 0, sweep0, n_sweeps, measure_start, energy_every,
+                      stream);
+}
+
+extern "C" hevmc_status hevmc_sweep_gr(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
+                                       uint64_t *gr, int32_t gr_bins, uint32_t sweep0, int32_t n_sweeps,
+                                       uint32_t measure_start, int32_t energy_every, void *stream)
+{
+    return sweep_with(p, coords, acc, rows, gr, gr_bins, nullptr, 0, sweep0, n_sweeps, measure_start, energy_every,
+                      stream);
+}
+
+extern "C" hevmc_status hevmc_sweep_trace(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
+                                          double *trace, int32_t trace_cap, uint32_t sweep0, int32_t n_sweeps,
+                                          uint32_t measure_start, int32_t energy_every, void *stream)
+{
+    return sweep_with(p, coords, acc, rows, nullptr, 0, trace, trace_cap, sweep0, n_sweeps, measure_start,
+                      energy_every, stream);
 }
 
 extern "C" hevmc_status hevmc_sweep_batch(int32_t n_requests, const hevmc_request *requests, const int32_t *map,

@@ -29,6 +29,8 @@ struct KParams {
     int32_t sorted;      // sweep keeps the atoms in LDS in spatial (Morton) order
     int32_t gr_bins;     // bins of the pair histogram accumulated at each sample (0: none)
     uint64_t *gr;        // [W][gr_bins] histogram counts (device), or null
+    double *trace;       // [W][trace_cap][6] per-sample local-energy records, or null
+    int32_t trace_cap;   // samples per walker the trace holds
 };
 
 // HFD-B(HE) pair potential (Aziz, McCourt, Wong 1987), the interaction named

@@ -350,11 +350,11 @@ __device__ void walker_resort(const KParams &p, T *sx, T *sy, T *sz, double *ru,
 // (T) and, for ROWS, the row sums (double) at rows_lds_offset(n, sizeof(T)).
 // g: the walker's coordinates [3][N]; accp: its accumulators; rg: its row sums
 // in HBM ([N] doubles) or null; grw: its pair histogram ([gr_bins], HIST
-// only).  For NT = 64 the walker is one wave and red, rsl, ebuf are not used.
+// only); trw: its per-sample records ([trace_cap][6]) or null.  For NT = 64 the walker is one wave and red, rsl, ebuf are not used.
 template <typename T, int NT, bool ROWS, bool HIST = false>
 __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *__restrict__ g,
                                              hevmc_walker_acc *__restrict__ accp, double *__restrict__ rg,
-                                             uint64_t *__restrict__ grw,
+                                             uint64_t *__restrict__ grw, double *__restrict__ trw,
                                              uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t m,
                                              unsigned char *smem_raw, double (*red)[NT / 64][2], double *rsl,
                                              double *ebuf)
@@ -605,6 +605,13 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                     for (int b = tid; b < nb; b += NT)
                         grw[b] += hist[b];
                 }
+                if (trw && tid < 6) {
+                    // the sample's record: (E_L, V, T_PB, T_JF, T_F, U), at its
+                    // index among all of the walker's samples
+                    const int64_t idx = a.n_samples + n_samp;
+                    if (idx < (int64_t)p.trace_cap)
+                        trw[(size_t)idx * 6 + tid] = el[tid];
+                }
                 if (tid == 0) {
                     nsum(a.sum_e, a.c_e, el[0]);
                     nsum(a.sum_e2, a.c_e2, el[0] * el[0]);
@@ -669,8 +676,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const size_t n = (size_t)p.n;
     sweep_walker<T, NT, ROWS, HIST>(p, p.wid_base + (uint32_t)w, coords + (size_t)w * 3 * n, accs + w,
                                     rows_hbm ? rows_hbm + (size_t)w * n : nullptr,
-                                    HIST ? p.gr + (size_t)w * (size_t)p.gr_bins : nullptr, sweep0, nsw, mstart, m,
-                                    smem_raw, red, rsl, ebuf);
+                                    HIST ? p.gr + (size_t)w * (size_t)p.gr_bins : nullptr,
+                                    p.trace ? p.trace + (size_t)w * (size_t)p.trace_cap * 6 : nullptr, sweep0, nsw,
+                                    mstart, m, smem_raw, red, rsl, ebuf);
 }
 
 // The batched sweep kernel (hevmc_sweep_batch): walker slots of several
@@ -694,7 +702,7 @@ __global__ __launch_bounds__(NT) void k_sweep_batch(BatchArgs b, const int32_t *
     const uint32_t wid = (uint32_t)map[2 * w + 1];
     const size_t n = (size_t)b.k[r].n;
     sweep_walker<T, NT, ROWS>(b.k[r], wid, coords + (size_t)w * 3 * n, accs + w,
-                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, nullptr, b.sweep0[r], nsw,
+                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, nullptr, nullptr, b.sweep0[r], nsw,
                               b.mstart[r], b.m[r], smem_raw, red, rsl, ebuf);
 }
 
@@ -716,8 +724,9 @@ __global__ __launch_bounds__(64 * kWalkersPerGroup) __attribute__((amdgpu_waves_
     const size_t n = (size_t)p.n;
     sweep_walker<T, 64, ROWS, HIST>(p, p.wid_base + (uint32_t)w, coords + (size_t)w * 3 * n, accs + w,
                                     rows_hbm ? rows_hbm + (size_t)w * n : nullptr,
-                                    HIST ? p.gr + (size_t)w * (size_t)p.gr_bins : nullptr, sweep0, nsw, mstart, m,
-                                    smem_raw + (size_t)wv * walker_lds, nullptr, nullptr, nullptr);
+                                    HIST ? p.gr + (size_t)w * (size_t)p.gr_bins : nullptr,
+                                    p.trace ? p.trace + (size_t)w * (size_t)p.trace_cap * 6 : nullptr, sweep0, nsw,
+                                    mstart, m, smem_raw + (size_t)wv * walker_lds, nullptr, nullptr, nullptr);
 }
 
 template <typename T, bool ROWS>
@@ -736,7 +745,7 @@ __global__ __launch_bounds__(64 * kWalkersPerGroup) __attribute__((amdgpu_waves_
     const uint32_t wid = (uint32_t)map[2 * w + 1];
     const size_t n = (size_t)b.k[r].n;
     sweep_walker<T, 64, ROWS>(b.k[r], wid, coords + (size_t)w * 3 * n, accs + w,
-                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, nullptr, b.sweep0[r], nsw,
+                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, nullptr, nullptr, b.sweep0[r], nsw,
                               b.mstart[r], b.m[r], smem_raw + (size_t)wv * walker_lds, nullptr, nullptr, nullptr);
 }
 
