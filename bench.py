@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the workload, run 5 plain device copies of MIB MiB (the reference "
                          "kernel for scaling HBM byte counters) and exit")
+    ap.add_argument("--b-scan", action="store_true",
+                    help="instead of the throughput line, one run of the workload with per-sample records and "
+                         "the correlated-sampling curve E(b') around its b, with one direct run to check it")
     return ap.parse_args()
 
 
@@ -132,6 +135,68 @@ def serve(args):
     print(json.dumps(line), flush=True)
 
 
+def b_scan(args, equil=200, measured=2000, factors=(0.97, 0.98, 0.99, 1.0, 1.01, 1.02, 1.03), check=1.02):
+    """E(b') per atom from one run at b (per-sample records + reweighting),
+    and a direct run at b' = check * b for comparison.  The reweighting factor
+    exp(2 (U_b' - U_b)) fluctuates like an extensive quantity, so one run
+    covers a range of b' that narrows as N grows: the scan runs N=108 with
+    1024 walkers (--n, --walkers override), where a few percent in b keeps an
+    effective sample size in the thousands."""
+    import numpy as np
+    import torch
+
+    from paper_1312_1282_amd import abi, configs, observables
+
+    torch.cuda.set_device(0)
+    wl = configs.C1_SMALL_FP64.with_(name="he4_b_scan", n=args.n or 108, walkers=args.walkers or 1024, m=5)
+    m = wl.m
+
+    def run(b, trace):
+        p = abi.params_for(wl, b=b)
+        coords, acc = abi.alloc_state(p)
+        rows = abi.alloc_rows(p)
+        abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
+        abi.sweep(p, coords, acc, 0, equil, abi.NO_MEASURE, 0, rows=rows)
+        cap = measured // m
+        tr = torch.zeros((wl.walkers, cap, 6), dtype=torch.float64, device="cuda") if trace else None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(0, measured, 25):
+            abi.sweep(p, coords, acc, equil + k, 25, equil, m, rows=rows, trace=tr)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        a = abi.acc_to_numpy(acc)
+        e_w = (a["sum_e"] + a["c_e"]) / a["n_samples"] / wl.n
+        return (None if tr is None else tr.cpu().numpy()), e_w, wl.walkers * wl.n * measured / dt
+
+    rec, e_w, rate_trace = run(wl.b, True)
+    curve = observables.reweight_b(rec, wl.b, [f * wl.b for f in factors], wl.n)
+    # per-walker spread of each estimate (walkers are independent chains)
+    for c in curve:
+        per = [observables.reweight_b(rec[w:w + 1], wl.b, [c["b"]], wl.n)[0]["E_per_atom"]
+               for w in range(wl.walkers)]
+        c["se_walkers"] = float(np.std(per, ddof=1) / np.sqrt(wl.walkers))
+    _, e_direct, rate_plain = run(check * wl.b, False)
+    rw = [c for c in curve if abs(c["b"] - check * wl.b) < 1e-12][0]
+    line = {
+        "metric": "correlated-sampling E(b') per atom from one run",
+        "value": rw["E_per_atom"],
+        "unit": "K per atom at b' = %.3f b" % check,
+        "n_gpus": 1,
+        "dtype": "f64" if wl.precision == configs.FP64 else "f32",
+        "data": "synthetic: fcc-started liquid 4He walkers",
+        "config": {"workload": wl.name, "b_A": wl.b, "equil_sweeps": equil, "measured_sweeps": measured,
+                   "energy_every": m, "samples": int(rec.shape[0] * rec.shape[1])},
+        "curve": curve,
+        "direct_check": {"b_A": check * wl.b, "E_per_atom": float(e_direct.mean()),
+                         "se": float(e_direct.std(ddof=1) / np.sqrt(len(e_direct))),
+                         "reweighted_minus_direct": rw["E_per_atom"] - float(e_direct.mean())},
+        "moves_per_s_with_trace": rate_trace,
+        "moves_per_s_without_trace": rate_plain,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def calibrate_copy(mib):
     """Plain device-to-device copies of a known size: FETCH_SIZE and WRITE_SIZE
     of these dispatches are what the counters read for mib MiB each way."""
@@ -194,6 +259,9 @@ def main():
         return
     if args.serve:
         serve(args)
+        return
+    if args.b_scan:
+        b_scan(args)
         return
     wl = configs.ALL[args.workload]
     if args.n or args.walkers:
