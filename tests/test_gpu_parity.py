@@ -120,6 +120,47 @@ def test_fp64_walker_too_large_for_lds():
     assert ei.value.code == -3
 
 
+def _largest_fitting_n(precision, lo, hi):
+    """Largest N whose walker fits one workgroup's LDS (bisection on the plan)."""
+    def fits(n):
+        try:
+            abi.footprint(gparams(n, 1, precision=precision))
+            return True
+        except abi.HevmcError as e:
+            assert e.code == -3
+            return False
+    assert fits(lo) and not fits(hi)
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        lo, hi = (mid, hi) if fits(mid) else (lo, mid)
+    return lo
+
+
+def test_largest_fp64_walker_follows_the_oracle():
+    """The largest FP64 walker that fits in LDS (plain variant, about 6800
+    atoms): one sweep with a local-energy sample, against the oracle; one
+    atom more is refused."""
+    n = _largest_fitting_n(abi.FP64, 4000, 10976)
+    assert 6000 < n < 7000
+    p = gparams(n, 2, seed=12)
+    plan = abi.plan_launch(p)
+    assert plan["variant"] == abi.VARIANT_PLAIN and plan["lds_per_walker"] >= 24 * n
+    xg, ag = _gpu_chain(p, [1], 0, 1)
+    s_ = osys(n, seed=12)
+    res = {}
+
+    def work(w):
+        res[w] = _oracle_chain(s_, w, 1, 0, 1)
+
+    th = [threading.Thread(target=work, args=(w,)) for w in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for w in range(2):
+        _compare_walker(xg[w], ag[w], *res[w])
+
+
 # ---------------------------------------------------------------------------
 # random numbers and start
 
