@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-time-limit", type=float, default=None,
                     help="stop serving after this many seconds; unfinished requests are reported as censored")
+    ap.add_argument("--serve-replicate", type=int, default=0, metavar="K",
+                    help="serve with equilibrate-then-replicate: K seed walkers per request")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the workload, run 5 plain device copies of MIB MiB (the reference "
                          "kernel for scaling HBM byte counters) and exit")
@@ -99,7 +101,7 @@ def serve(args):
 
     torch.cuda.set_device(0)
     reqs = serving.request_stream(args.serve, rate=args.serve_rate)
-    server = serving.Server()
+    server = serving.Server(replicate=args.serve_replicate)
     t0 = time.perf_counter()
     server.run(reqs, realtime=True, time_limit=args.serve_time_limit,
                log=lambda m: print(m, file=sys.stderr, flush=True))
@@ -118,7 +120,8 @@ def serve(args):
         "data": "synthetic: seeded Poisson stream of liquid 4He VMC requests",
         "config": {"workload": "he4_serving_stream", "requests": args.serve, "arrival_rate_per_s": args.serve_rate,
                    "target_se_K": server.target_se, "equil_sweeps": server.equil, "energy_every": server.m,
-                   "check_every": server.check_every, "quantum_sweeps": server.quantum},
+                   "check_every": server.check_every, "quantum_sweeps": server.quantum,
+                   "replicate_seeds": server.replicate, "decorrelate_sweeps": server.decorrelate},
         "serving": {
             **lat,
             "offered_rate_per_s": args.serve_rate,

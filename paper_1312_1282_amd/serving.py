@@ -22,6 +22,7 @@ walkers' mean energies per atom e_w, and stop when SE <= target and every
 walker has at least min_samples samples (the W independent chains play the
 role of the paper's independent Markov chains, Eq. (10) and the text after it).
 """
+import math
 import time
 from dataclasses import dataclass
 
@@ -51,6 +52,7 @@ class Request:
     energy: float = None
     result: np.ndarray = None
     slot0: int = None
+    replicated: bool = False
     rejected: str = None
     failed: str = None      # set when a walker's state turns non-finite
 
@@ -136,7 +138,7 @@ class _Pool:
 class Server:
     def __init__(self, target_se=configs.SERVE_TARGET_SE, equil=200, m=5, check_every=50, min_samples=20,
                  quantum=None, lds_oversubscription=4.0, max_requests_per_class=abi.MAX_BATCH,
-                 slots_per_class=8192, latency_threads=True):
+                 slots_per_class=8192, latency_threads=True, replicate=0, decorrelate=50):
         self.target_se = target_se
         self.equil = equil
         self.m = m
@@ -144,6 +146,12 @@ class Server:
         self.min_samples = min_samples
         self.quantum = quantum
         self.latency_threads = latency_threads
+        # equilibrate-then-replicate: with replicate = K > 0, a request first
+        # equilibrates only K seed walkers for `equil` sweeps; then every
+        # walker j takes a copy of seed j mod K and decorrelates, with its own
+        # random numbers, for `decorrelate` sweeps before measuring
+        self.replicate = replicate
+        self.decorrelate = decorrelate if replicate else 0
         self.budget = lds_oversubscription * LDS_PER_CU * CUS
         self.max_per_class = max_requests_per_class
         self.slots_per_class = slots_per_class
@@ -205,6 +213,22 @@ class Server:
         pool.map_host[a:a + req.walkers, 1] = np.arange(req.walkers, dtype=np.int32)
         return True
 
+    def _replicate(self, pool, req):
+        """Copy the equilibrated seeds to the request's other walkers (walker j
+        takes seed j mod K) and restart every walker's running totals and
+        accumulators from its configuration; from here on each walker moves
+        with its own random numbers."""
+        import torch
+
+        K, W, a = self.seeds(req), req.walkers, req.slot0
+        src = torch.arange(K, W, device="cuda") % K + a
+        with torch.cuda.stream(pool.stream):
+            pool.coords[a + K:a + W] = pool.coords[src]
+            pool.rows[a + K:a + W] = pool.rows[src]
+            abi.init_walkers(self.params(req), pool.coords[a:a + W], pool.acc[a:a + W], fcc_start=False,
+                             stream=pool.stream, rows=pool.rows[a:a + W])
+        req.replicated = True
+
     def _retire(self, pool, req, acc_np, now):
         req.done = now
         req.result = acc_np
@@ -220,17 +244,27 @@ class Server:
         se = float(e.std(ddof=1) / np.sqrt(len(e))) if len(e) > 1 else float("inf")
         return se, float(e.mean()), bool(ns.min() >= self.min_samples and se <= self.target_se)
 
+    def measure_start(self):
+        """Sweep index from which every request measures."""
+        return self.equil + self.decorrelate
+
+    def seeds(self, req):
+        """Walkers that run during equilibration."""
+        if self.replicate and not req.replicated and req.walkers > self.replicate:
+            return self.replicate
+        return req.walkers
+
     def quantum_for(self, n):
         """Sweeps per launch of a class: about the same GPU time per launch for
         every N (a small walker's sweep is short).  A function of N only, so a
         request is split into the same launches alone and in any mix; the
-        equilibration length is a multiple of it."""
+        equilibration length and the first measured sweep are multiples of
+        it."""
         if self.quantum:
             return self.quantum
-        q = 100 if n <= 128 else 50 if n <= 300 else 25 if n <= 600 else 10
-        while self.equil % q:
-            q //= 2
-        return max(q, 1)
+        target = 100 if n <= 128 else 50 if n <= 300 else 25 if n <= 600 else 10
+        g = math.gcd(self.equil, self.measure_start()) or target
+        return max(d for d in range(1, min(target, g) + 1) if g % d == 0)
 
     def cadence(self, n):
         """Measured sweeps between stop-rule checks: check_every, or the
@@ -249,9 +283,10 @@ class Server:
         for k, r in enumerate(reqs):
             arr[k].params = self.params(r)
             arr[k].sweep0 = r.sweeps
-            arr[k].measure_start = self.equil
+            arr[k].measure_start = self.measure_start()
             arr[k].energy_every = self.m
-            pool.map_host[r.slot0:r.slot0 + r.walkers, 0] = k
+            pool.map_host[r.slot0:r.slot0 + r.walkers, 0] = -1
+            pool.map_host[r.slot0:r.slot0 + self.seeds(r), 0] = k
         with torch.cuda.stream(pool.stream):
             pool.map.copy_(torch.from_numpy(pool.map_host.copy()).pin_memory(), non_blocking=True)
             abi.sweep_batch(arr, pool.map, pool.coords, pool.acc, pool.rows, self.quantum_for(pool.n),
@@ -261,7 +296,7 @@ class Server:
         pool.event = ev
         pool.in_flight = reqs
         self.launches += 1
-        self.moves += sum(r.walkers * r.n for r in reqs) * self.quantum_for(pool.n)
+        self.moves += sum(self.seeds(r) * r.n for r in reqs) * self.quantum_for(pool.n)
 
     def _finish_quantum(self, pool, now):
         """The launch of pool is complete: advance counters, run stop checks."""
@@ -269,7 +304,9 @@ class Server:
         q, c = self.quantum_for(pool.n), self.cadence(pool.n)
         for r in pool.in_flight:
             r.sweeps += q
-            meas = r.sweeps - self.equil
+            if self.seeds(r) < r.walkers and r.sweeps >= self.equil:
+                self._replicate(pool, r)
+            meas = r.sweeps - self.measure_start()
             if meas > 0 and meas % c == 0:
                 due.append(r)
         if due:

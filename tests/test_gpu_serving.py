@@ -97,3 +97,21 @@ def test_server_rejects_walkers_that_do_not_fit():
         [big, small], realtime=False)
     assert out[0].rejected and "ENOFIT" in out[0].rejected
     assert out[1].done is not None
+
+
+def test_replicated_server_alone_and_in_mix_and_energy():
+    """Equilibrate-then-replicate: a request's result is the same bits alone
+    and in a mix, and its energy agrees with the same request served without
+    replication within their standard errors."""
+    mk = lambda: [_req(0, 108, 200, abi.FP64, 0.0219, 2.94, 31), _req(1, 256, 96, abi.FP32, 0.0210, 3.0, 32)]
+    kw = dict(target_se=3e-3, equil=40, check_every=20, min_samples=4, replicate=8, decorrelate=20)
+    mix = serving.Server(**kw).run(mk(), realtime=False)
+    for r in mix:
+        assert r.done is not None and r.replicated
+    alone = serving.Server(**kw).run([mk()[0]], realtime=False)[0]
+    assert alone.sweeps == mix[0].sweeps and alone.result.tobytes() == mix[0].result.tobytes()
+    plain = serving.Server(**{k: v for k, v in kw.items() if k not in ("replicate", "decorrelate")}).run(
+        [mk()[0]], realtime=False)[0]
+    assert not plain.replicated
+    assert abs(alone.energy - plain.energy) < 4.0 * np.hypot(alone.se, plain.se), (alone.energy, plain.energy)
+

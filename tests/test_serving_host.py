@@ -111,3 +111,20 @@ def test_class_threads_depend_on_n_only():
     assert serving.Server(latency_threads=False).threads_for(108) == 0
     r = serving.Request(rid=0, arrival=0.0, n=500, walkers=64, precision=0, density=0.02, b=2.9, seed=3)
     assert srv.params(r).threads == 256 and srv.params(r).n_walkers == 64
+
+
+def test_replication_phases():
+    srv = serving.Server(equil=200, replicate=16, decorrelate=50)
+    assert srv.measure_start() == 250
+    for n in configs.SERVE_N:
+        q = srv.quantum_for(n)
+        assert 200 % q == 0 and 250 % q == 0
+    assert srv.quantum_for(108) == 50
+    r = serving.Request(rid=0, arrival=0.0, n=108, walkers=100, precision=0, density=0.02, b=2.9, seed=3)
+    assert srv.seeds(r) == 16
+    r.replicated = True
+    assert srv.seeds(r) == 100
+    small = serving.Request(rid=1, arrival=0.0, n=108, walkers=10, precision=0, density=0.02, b=2.9, seed=4)
+    assert srv.seeds(small) == 10
+    off = serving.Server(equil=200)
+    assert off.measure_start() == 200 and off.seeds(small) == 10 and off.quantum_for(108) == 100
