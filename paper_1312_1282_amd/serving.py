@@ -221,8 +221,10 @@ class Server:
         import torch
 
         K, W, a = self.seeds(req), req.walkers, req.slot0
-        src = torch.arange(K, W, device="cuda") % K + a
         with torch.cuda.stream(pool.stream):
+            # the index vector is made on the pool's stream too: made on another
+            # stream, the gather could read it before it is written
+            src = torch.arange(K, W, device="cuda") % K + a
             pool.coords[a + K:a + W] = pool.coords[src]
             pool.rows[a + K:a + W] = pool.rows[src]
             abi.init_walkers(self.params(req), pool.coords[a:a + W], pool.acc[a:a + W], fcc_start=False,
