@@ -315,6 +315,19 @@ def test_lockstep_spatial_order_ragged_n(variant):
     assert np.array_equal(x1, xg) and a1.tobytes() == ag.tobytes()
 
 
+@pytest.mark.parametrize("n,threads", [(512, 64), (1024, 128)])
+def test_lockstep_dense_lanes(n, threads):
+    """N = 8 x threads: every lane owns eight atoms and the row-sum passes run
+    without per-lane bounds checks; the chain still follows the oracle."""
+    W = 2
+    p = gparams(n, W, threads=threads, seed=23, variant=abi.VARIANT_ROWS)
+    xg, ag = _gpu_chain(p, [2, 2], 1, 3)
+    s_ = osys(n, seed=23)
+    for w in range(W):
+        xo, ao = _oracle_chain(s_, w, 4, 1, 3)
+        _compare_walker(xg[w], ag[w], xo, ao)
+
+
 def test_stale_rows_buffer_is_recomputed():
     """A rows buffer that disagrees with u_run is detected and rebuilt: the
     result equals a run that recomputes the rows at every launch."""
