@@ -21,6 +21,14 @@
 //    workgroup sum rides on the next micro-update's reduction.  The rows are
 //    refreshed exactly by every local-energy pass, can be kept in HBM between
 //    launches, and are checked against u_run (sum_i R_i = 2 U) on load.
+//
+// Walkers of at most 512 atoms can run one wave each, four to a workgroup,
+// synchronised by wavefront fences only.  Larger walkers re-sort their atoms
+// in LDS by cell at every sweep (spatial order), so that a wave's atoms are
+// neighbours and whole waves skip the short-range exponentials.  The
+// local-energy pass can also count a pair-distance histogram (g(r)) and the
+// sweep can record every sample's local-energy terms; both leave the chain's
+// bits unchanged.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
