@@ -394,8 +394,11 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
         sx[i] = v;
         bad |= !isfinite((double)v);
     }
-    hevmc_walker_acc a = *accp;
-    double u_run = a.u_run, v_run = a.v_run;
+    // the accumulators stay in HBM: thread 0 adds to them at samples and at
+    // the end of measured sweeps, so the move loop holds only the running
+    // totals in registers
+    double u_run = accp->u_run, v_run = accp->v_run;
+    const int64_t samples0 = accp->n_samples;
     // a walker with a non-finite coordinate (whose pairs would silently drop
     // out of every sum) leaves the launch with NaN running totals, which the
     // caller detects
@@ -616,17 +619,17 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                 if (trw && tid < 6) {
                     // the sample's record: (E_L, V, T_PB, T_JF, T_F, U), at its
                     // index among all of the walker's samples
-                    const int64_t idx = a.n_samples + n_samp;
+                    const int64_t idx = samples0 + n_samp;
                     if (idx < (int64_t)p.trace_cap)
                         trw[(size_t)idx * 6 + tid] = el[tid];
                 }
                 if (tid == 0) {
-                    nsum(a.sum_e, a.c_e, el[0]);
-                    nsum(a.sum_e2, a.c_e2, el[0] * el[0]);
-                    nsum(a.sum_v, a.c_v, el[1]);
-                    nsum(a.sum_tpb, a.c_tpb, el[2]);
-                    nsum(a.sum_tjf, a.c_tjf, el[3]);
-                    nsum(a.sum_tf, a.c_tf, el[4]);
+                    nsum(accp->sum_e, accp->c_e, el[0]);
+                    nsum(accp->sum_e2, accp->c_e2, el[0] * el[0]);
+                    nsum(accp->sum_v, accp->c_v, el[1]);
+                    nsum(accp->sum_tpb, accp->c_tpb, el[2]);
+                    nsum(accp->sum_tjf, accp->c_tjf, el[3]);
+                    nsum(accp->sum_tf, accp->c_tf, el[4]);
                 }
                 n_samp += 1;
                 u_run = el[5];
@@ -634,7 +637,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                 last_s = -1;
             }
             if (tid == 0)
-                nsum(a.sum_vs, a.c_vs, v_run);
+                nsum(accp->sum_vs, accp->c_vs, v_run);
             n_swm += 1;
         }
     }
@@ -658,13 +661,12 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
         }
     }
     if (tid == 0) {
-        a.u_run = bad_walker ? __builtin_nan("") : u_run;
-        a.v_run = bad_walker ? __builtin_nan("") : v_run;
-        a.n_samples += n_samp;
-        a.n_sweeps_meas += n_swm;
-        a.n_acc += n_acc;
-        a.n_try += n_try;
-        *accp = a;
+        accp->u_run = bad_walker ? __builtin_nan("") : u_run;
+        accp->v_run = bad_walker ? __builtin_nan("") : v_run;
+        accp->n_samples += n_samp;
+        accp->n_sweeps_meas += n_swm;
+        accp->n_acc += n_acc;
+        accp->n_try += n_try;
     }
 }
 
