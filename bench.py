@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-time-limit", type=float, default=None,
                     help="stop serving after this many seconds; unfinished requests are reported as censored")
+    ap.add_argument("--precision-check", action="store_true",
+                    help="instead of the throughput line, the FP32 form against FP64 at N=2048 with 1024 walkers "
+                         "on identical seeds: chain energies and per-configuration local-energy error in mK/atom")
     ap.add_argument("--serve-replicate", type=int, default=0, metavar="K",
                     help="serve with equilibrate-then-replicate: K seed walkers per request")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -200,6 +203,59 @@ def b_scan(args, equil=200, measured=2000, factors=(0.97, 0.98, 0.99, 1.0, 1.01,
     print(json.dumps(line), flush=True)
 
 
+def precision_check(args, equil=100, measured=400):
+    """The precision form against FP64 on the same seeds and walker ids (the
+    N=2048, 1024-walker FP32 workload): (1) the two chains' energies per atom,
+    walker-paired; (2) the FP32 local energy of each FP64 chain's final
+    configuration (rounded to FP32) against its FP64 local energy, in mK/atom:
+    the form's own error, free of sampling noise."""
+    import numpy as np
+    import torch
+
+    from paper_1312_1282_amd import abi, configs
+
+    torch.cuda.set_device(0)
+    wl = configs.C3_N2048_FP32
+    out = {}
+    for prec in (configs.FP64, configs.FP32):
+        p = abi.params_for(wl, precision=prec)
+        coords, acc = abi.alloc_state(p)
+        rows = abi.alloc_rows(p)
+        abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
+        abi.sweep(p, coords, acc, 0, equil, abi.NO_MEASURE, 0, rows=rows)
+        for k in range(0, measured, 50):
+            abi.sweep(p, coords, acc, equil + k, 50, equil, wl.m, rows=rows)
+        torch.cuda.synchronize()
+        a = abi.acc_to_numpy(acc)
+        out[prec] = ((a["sum_e"] + a["c_e"]) / a["n_samples"] / wl.n, coords)
+    d = out[configs.FP32][0] - out[configs.FP64][0]
+    # per-configuration error on the FP64 chains' final configurations
+    x64 = out[configs.FP64][1]
+    x32 = x64.to(torch.float32)
+    p64 = abi.params_for(wl, precision=configs.FP64)
+    p32 = abi.params_for(wl, precision=configs.FP32)
+    e64 = torch.zeros((wl.walkers, 6), dtype=torch.float64, device="cuda")
+    e32 = torch.zeros((wl.walkers, 6), dtype=torch.float64, device="cuda")
+    abi.local_energy(p64, x32.to(torch.float64), e64)   # FP64 terms of the FP32-rounded configuration
+    abi.local_energy(p32, x32, e32)
+    torch.cuda.synchronize()
+    err = (e32[:, 0] - e64[:, 0]).cpu().numpy() / wl.n * 1e3
+    line = {
+        "metric": "FP32 form against FP64 on identical seeds",
+        "value": float(np.abs(err).max()),
+        "unit": "mK/atom (largest per-configuration local-energy error)",
+        "n_gpus": 1,
+        "dtype": "f32 pair terms, f64 sums",
+        "data": "synthetic: fcc-started liquid 4He walkers",
+        "config": {"workload": wl.name, "equil_sweeps": equil, "measured_sweeps": measured, "energy_every": wl.m},
+        "chain_difference_mK": float(d.mean() * 1e3),
+        "chain_difference_se_mK": float(d.std(ddof=1) / np.sqrt(len(d)) * 1e3),
+        "config_error_mK": {"mean": float(err.mean()), "rms": float(np.sqrt((err ** 2).mean())),
+                            "max_abs": float(np.abs(err).max())},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def calibrate_copy(mib):
     """Plain device-to-device copies of a known size: FETCH_SIZE and WRITE_SIZE
     of these dispatches are what the counters read for mib MiB each way."""
@@ -265,6 +321,9 @@ def main():
         return
     if args.b_scan:
         b_scan(args)
+        return
+    if args.precision_check:
+        precision_check(args)
         return
     wl = configs.ALL[args.workload]
     if args.n or args.walkers:
