@@ -299,11 +299,13 @@ def test_split_launches_bitwise_identical(variant, threads):
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_lockstep_spatial_order_ragged_n(variant):
-    """N = 300 (the sort pads its 512 keys) with atoms re-sorted by cell every
-    sweep: the chain still follows the oracle move for move, and a split run is
-    bitwise the same as one launch."""
-    n, W = 300, 3
+@pytest.mark.parametrize("n", [3, 65, 300])
+def test_lockstep_spatial_order_ragged_n(variant, n):
+    """N = 3, 65, 300 (the sort pads its keys to a power of two; at N < 128
+    most lanes own no atom) with atoms re-sorted by cell every sweep: the chain
+    still follows the oracle move for move, and a split run is bitwise the same
+    as one launch."""
+    W = 3
     p = gparams(n, W, threads=128, seed=17, wbase=7, variant=variant)
     assert abi.plan_launch(p)["spatial_order"] == 1
     xg, ag = _gpu_chain(p, [4, 5], 3, 2)
