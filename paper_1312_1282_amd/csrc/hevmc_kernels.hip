@@ -424,7 +424,20 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
         walker_sync<NT>();
     }
 
-    const bool full = ROWS && n == kRowsPerLane * NT;   // every lane owns kRowsPerLane atoms
+    // row-sum passes: kRowsPerLane when every lane owns that many atoms; 1, 2
+    // or 4 when at most that many chunks of NT atoms cover N (the last one
+    // partial: its idle lanes re-read atom N-1 and count nothing); 0 otherwise.
+    // The first four have no per-lane branch, so their LDS loads issue up front.
+    // The few-chunk forms are compiled only for walkers of at most 128 threads
+    // (small N): in the large-walker kernels their registers would crowd the
+    // eight-chunk form, which then spills.
+    constexpr bool kFewChunkModes = NT <= 128;
+    const int nchunks = (n + NT - 1) / NT;
+    const int lane_mode = n == kRowsPerLane * NT ? kRowsPerLane
+                          : nchunks <= 1       ? 1
+                          : nchunks <= 2       ? 2
+                          : nchunks <= 4       ? 4
+                                               : 0;
     int last_s = -1;          // atom accepted in the previous micro-update
     T lx = 0, ly = 0, lz = 0; // its new position (LDS copy not yet visible to all waves)
     double dv_pend = 0.0;     // ROWS: lane partial of dV of the last accepted move
@@ -468,26 +481,45 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                     T un_[kRowsPerLane], r2n_[kRowsPerLane];
                     // FULL: every lane owns kRowsPerLane atoms, so the unrolled
                     // body has no per-lane branch and its loads issue up front
-                    auto forward = [&](auto full_c) {
-                        constexpr bool FULL = decltype(full_c)::value;
+                    auto forward = [&](auto mode_c) {
+                        constexpr int MODE = decltype(mode_c)::value;
+                        constexpr int CH = MODE == 0 ? kRowsPerLane : MODE;
 #pragma unroll
-                        for (int jj = 0; jj < kRowsPerLane; ++jj) {
+                        for (int jj = 0; jj < CH; ++jj) {
                             const int i = tid + jj * NT;
                             T uu = T(0), r2 = T(1), ri = T(1);
-                            if (FULL || i < n) {
-                                r2 = dist2(p, nx, ny, nz, sx[i], sy[i], sz[i]);
+                            if constexpr (MODE == 0) {
+                                if (i < n) {
+                                    r2 = dist2(p, nx, ny, nz, sx[i], sy[i], sz[i]);
+                                    ri = inv_sqrt(r2);
+                                    uu = pair_u_in(p, r2, ri, i != s);
+                                }
+                            } else {
+                                const bool live = MODE == kRowsPerLane || i < n;
+                                const int ic = MODE == kRowsPerLane ? i : min(i, n - 1);
+                                r2 = dist2(p, nx, ny, nz, sx[ic], sy[ic], sz[ic]);
                                 ri = inv_sqrt(r2);
-                                uu = pair_u_in(p, r2, ri, i != s);
+                                uu = pair_u_in(p, r2, ri, live && i != s);
                             }
                             un_[jj] = uu;
                             r2n_[jj] = r2;
                             su += (double)uu;
                         }
                     };
-                    if (full)
-                        forward(std::true_type{});
-                    else
-                        forward(std::false_type{});
+                    if constexpr (kFewChunkModes) {
+                        switch (lane_mode) {
+                        case kRowsPerLane: forward(std::integral_constant<int, kRowsPerLane>{}); break;
+                        case 4: forward(std::integral_constant<int, 4>{}); break;
+                        case 2: forward(std::integral_constant<int, 2>{}); break;
+                        case 1: forward(std::integral_constant<int, 1>{}); break;
+                        default: forward(std::integral_constant<int, 0>{}); break;
+                        }
+                    } else {
+                        if (lane_mode == kRowsPerLane)
+                            forward(std::integral_constant<int, kRowsPerLane>{});
+                        else
+                            forward(std::integral_constant<int, 0>{});
+                    }
                     const double w0 = wave_sum(su);
                     const double w1 = (last_s >= 0) ? wave_sum(dv_pend) : 0.0;
                     double SU = 0.0, DVP = 0.0, RS;
@@ -524,28 +556,42 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                         u_run += DU;
                         // old-position terms: update the rows, form dV
                         double dvl = 0.0;
-                        auto accept_pass = [&](auto full_c) {
-                            constexpr bool FULL = decltype(full_c)::value;
+                        auto accept_pass = [&](auto mode_c) {
+                            constexpr int MODE = decltype(mode_c)::value;
+                            constexpr int CH = MODE == 0 ? kRowsPerLane : MODE;
 #pragma unroll
-                            for (int jj = 0; jj < kRowsPerLane; ++jj) {
+                            for (int jj = 0; jj < CH; ++jj) {
                                 const int i = tid + jj * NT;
-                                if (FULL || i < n) {
-                                    const T r2o = dist2(p, ox, oy, oz, sx[i], sy[i], sz[i]);
+                                const bool live = MODE == kRowsPerLane || i < n;
+                                if (MODE != 0 || live) {
+                                    const int ic = (MODE == 0 || MODE == kRowsPerLane) ? i : min(i, n - 1);
+                                    const T r2o = dist2(p, ox, oy, oz, sx[ic], sy[ic], sz[ic]);
                                     const T rio = inv_sqrt(r2o);
                                     const T uo = pair_u_ri(p, r2o, rio);
                                     const T vo = pair_v_ri(p, r2o, rio);
                                     const T vn = pair_v_ri(p, r2n_[jj], inv_sqrt(r2n_[jj]));
-                                    const bool other = (i != s);
+                                    const bool other = live && (i != s);
                                     const double dr = other ? (double)un_[jj] - (double)uo : 0.0;
-                                    ru[i] += dr;
+                                    if (live)
+                                        ru[i] += dr;
                                     dvl += other ? (double)vn - (double)vo : 0.0;
                                 }
                             }
                         };
-                        if (full)
-                            accept_pass(std::true_type{});
-                        else
-                            accept_pass(std::false_type{});
+                        if constexpr (kFewChunkModes) {
+                            switch (lane_mode) {
+                            case kRowsPerLane: accept_pass(std::integral_constant<int, kRowsPerLane>{}); break;
+                            case 4: accept_pass(std::integral_constant<int, 4>{}); break;
+                            case 2: accept_pass(std::integral_constant<int, 2>{}); break;
+                            case 1: accept_pass(std::integral_constant<int, 1>{}); break;
+                            default: accept_pass(std::integral_constant<int, 0>{}); break;
+                            }
+                        } else {
+                            if (lane_mode == kRowsPerLane)
+                                accept_pass(std::integral_constant<int, kRowsPerLane>{});
+                            else
+                                accept_pass(std::integral_constant<int, 0>{});
+                        }
                         dv_pend = dvl;
                         if (owner) {
                             sx[s] = nx; sy[s] = ny; sz[s] = nz;
