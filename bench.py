@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="override the workload's atoms per walker")
     ap.add_argument("--walkers", type=int, default=0, help="override the workload's walker count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-energy", action="store_true",
+                    help="sweeps only: no local-energy samples in the timed launches (the pair loop alone)")
     ap.add_argument("--cpu-sweeps", type=int, default=70,
                     help="sweeps per walker of the CPU oracle sample (about 10 s on 16 host cores at N=2048)")
     ap.add_argument("--serve", type=int, default=0, metavar="REQUESTS",
@@ -290,6 +292,13 @@ def cpu_baseline(wl, sweeps):
     O.run_walkers(s_, 0, xyz, accs, 0, sweeps, 0, m, cores)
     dt = time.perf_counter() - t0
     moves = W * wl.n * sweeps
+    # the paper's convention (one core): one walker, a few sweeps, one thread
+    x1 = O.fcc_start(s_, 0)
+    a1 = O.walker_init(s_, x1)
+    s1 = max(1, sweeps // 10)
+    t1 = time.perf_counter()
+    O.run_walker(s_, 0, x1, a1, 0, s1, 0, m)
+    dt1 = time.perf_counter() - t1
     return {
         "value": moves / dt,
         "unit": "moves/s",
@@ -297,6 +306,7 @@ def cpu_baseline(wl, sweeps):
         "kind": "oracle",
         "sample": f"{W} walkers x {sweeps} sweeps of N={wl.n} with a local energy every {m} sweeps, "
                   f"one walker per thread, {dt:.1f} s wall",
+        "single_core_moves_per_s": wl.n * s1 / dt1,
     }
 
 
@@ -336,7 +346,7 @@ def main():
     rows = abi.alloc_rows(p)
     abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
     S = args.sweeps_per_step
-    m = wl.m
+    m = 0 if args.no_energy else wl.m
     t = 0
     # warm-up launches are the same work as timed ones (equilibration with
     # local energies); the accumulators are then restarted from the current
@@ -375,8 +385,8 @@ def main():
     ns = np.maximum(a["n_samples"], 1)
     e_w = (a["sum_e"] + a["c_e"]) / ns / wl.n
     physics = {
-        "E_per_atom_K": float(e_w.mean()),
-        "E_se_K": float(e_w.std(ddof=1) / np.sqrt(len(e_w))) if len(e_w) > 1 else None,
+        "E_per_atom_K": float(e_w.mean()) if m > 0 else None,
+        "E_se_K": float(e_w.std(ddof=1) / np.sqrt(len(e_w))) if len(e_w) > 1 and m > 0 else None,
         "acceptance": acc_rate,
         "samples_per_walker": int(a["n_samples"][0]),
     }
