@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -293,6 +294,20 @@ void make_kparams(const hevmc_params *p, KParams &k)
     k.gr = nullptr;
     k.trace = nullptr;
     k.trace_cap = 0;
+    k.share_tag = 0;
+}
+
+// A fresh nonzero 24-bit tag per sweep launch: walkers compare progress only
+// with a partner of the same launch (walkers of other launches running on the
+// same compute units, or words left over from earlier launches, are ignored).
+static uint32_t next_share_tag()
+{
+    static std::atomic<uint32_t> counter{0};
+    uint32_t t;
+    do {
+        t = (counter.fetch_add(1, std::memory_order_relaxed) + 1u) & 0xFFFFFFu;
+    } while (t == 0u);
+    return t;
 }
 
 hevmc_status launched(hipError_t e, const char *what) { return e == hipSuccess ? HEVMC_OK : hip_fail(e, what); }
@@ -370,6 +385,16 @@ extern "C" hevmc_status hevmc_init_walkers(const hevmc_params *p, void *coords, 
     return launched(launch_init(L, coords, acc, rows, fcc_start ? 1 : 0, nc, L.k.L / nc), "init kernel launch");
 }
 
+// Whether the plan puts two or more multi-wave walkers on one compute unit
+// (the case the sweep kernels balance by issue priority).
+static bool shares_cu(const Launch &L)
+{
+    DeviceLimits d;
+    if (L.threads <= 64 || device_limits(d) != HEVMC_OK)
+        return false;
+    return d.lds_per_cu / (L.lds_bytes + static_lds(L.threads)) >= 2;
+}
+
 // The sweep with its optional outputs: pair histogram and per-sample trace.
 static hevmc_status sweep_with(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
                                uint64_t *gr, int32_t gr_bins, double *trace, int32_t trace_cap, uint32_t sweep0,
@@ -396,6 +421,7 @@ static hevmc_status sweep_with(const hevmc_params *p, void *coords, hevmc_walker
         return fail(HEVMC_EINVAL, "sweep counter would pass 2^32 - 1");
     if (n_sweeps == 0)
         return HEVMC_OK;
+    L.k.share_tag = shares_cu(L) ? next_share_tag() : 0u;
     return launched(launch_sweep(L, coords, acc, rows, sweep0, n_sweeps, measure_start, energy_every),
                     "sweep kernel launch");
 }
@@ -462,10 +488,15 @@ extern "C" hevmc_status hevmc_sweep_batch(int32_t n_requests, const hevmc_reques
     hevmc_status st = plan(&shape, stream, L);
     if (st != HEVMC_OK)
         return st;
-    for (int r = 0; r < n_requests; ++r)
-        b.k[r].sorted = L.k.sorted;
     if (n_sweeps == 0)
         return HEVMC_OK;
+    // every slot of the launch runs n_sweeps sweeps of the same N, so their
+    // progress is comparable: one tag for all requests
+    const uint32_t tag = shares_cu(L) ? next_share_tag() : 0u;
+    for (int r = 0; r < n_requests; ++r) {
+        b.k[r].sorted = L.k.sorted;
+        b.k[r].share_tag = tag;
+    }
     return launched(launch_sweep_batch(L, b, map, n_slots, coords, acc, rows, n_sweeps), "batched sweep launch");
 }
 

@@ -31,6 +31,7 @@ struct KParams {
     uint64_t *gr;        // [W][gr_bins] histogram counts (device), or null
     double *trace;       // [W][trace_cap][6] per-sample local-energy records, or null
     int32_t trace_cap;   // samples per walker the trace holds
+    uint32_t share_tag;  // nonzero: this launch's tag for balancing walkers that share a CU (0: off)
 };
 
 // HFD-B(HE) pair potential (Aziz, McCourt, Wong 1987), the interaction named

@@ -359,13 +359,36 @@ __device__ void walker_resort(const KParams &p, T *sx, T *sy, T *sz, double *ru,
 // g: the walker's coordinates [3][N]; accp: its accumulators; rg: its row sums
 // in HBM ([N] doubles) or null; grw: its pair histogram ([gr_bins], HIST
 // only); trw: its per-sample records ([trace_cap][6]) or null.  For NT = 64 the walker is one wave and red, rsl, ebuf are not used.
+// Two walkers that share a compute unit compete for its four SIMDs, and the
+// hardware issues from the oldest ready wave first.  Left to that, the walker
+// dispatched first finishes in about two thirds of the launch and its partner
+// runs the rest alone, with no second wave per SIMD to cover its barrier and
+// reduction latencies.  So every 64 moves thread 0 swaps its progress into its
+// compute unit's word of cu_progress and reads back what was there.  If that
+// came from the partner (same launch tag, other walker) and the partner is
+// ahead, the walker raises its waves' issue priority for the next 64 moves;
+// otherwise it lowers it.  Only the order in which waves issue changes, so
+// every result is bitwise the same.
+//   word: launch tag (24 bits) | walker id (16 bits) | 64-move blocks done (24 bits)
+__device__ unsigned long long cu_progress[1024];
+
+__device__ __forceinline__ int share_turn(uint32_t tag, uint32_t wid, uint32_t blk, uint32_t cu, int prev)
+{
+    const unsigned long long mine = ((unsigned long long)(tag & 0xFFFFFFu) << 40) |
+                                    ((unsigned long long)(wid & 0xFFFFu) << 24) | (blk & 0xFFFFFFu);
+    const unsigned long long seen = atomicExch(&cu_progress[cu & 1023u], mine);
+    if ((uint32_t)(seen >> 40) == (tag & 0xFFFFFFu) && (uint32_t)((seen >> 24) & 0xFFFFu) != (wid & 0xFFFFu))
+        return (uint32_t)(seen & 0xFFFFFFu) > (blk & 0xFFFFFFu) ? 1 : 0;
+    return prev;
+}
+
 template <typename T, int NT, bool ROWS, bool HIST = false>
 __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *__restrict__ g,
                                              hevmc_walker_acc *__restrict__ accp, double *__restrict__ rg,
                                              uint64_t *__restrict__ grw, double *__restrict__ trw,
                                              uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t m,
                                              unsigned char *smem_raw, double (*red)[NT / 64][2], double *rsl,
-                                             double *ebuf)
+                                             double *ebuf, int *prio)
 {
     constexpr int NW = NT / 64;
     T *sx = reinterpret_cast<T *>(smem_raw);
@@ -442,6 +465,11 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
     T lx = 0, ly = 0, lz = 0; // its new position (LDS copy not yet visible to all waves)
     double dv_pend = 0.0;     // ROWS: lane partial of dV of the last accepted move
 
+    // issue priority against the walker sharing this compute unit (prio: two
+    // flags in LDS, written by thread 0 for blocks of alternating parity)
+    const bool share = NT > 64 && prio != nullptr && p.share_tag != 0;
+    const uint32_t cu = share ? __smid() : 0u;
+    const uint32_t nblk = (uint32_t)((n + 63) / 64);
     for (int it = 0; it < nsw; ++it) {
         const uint32_t t = sweep0 + (uint32_t)it;
         const bool measured = t >= mstart;
@@ -450,6 +478,19 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
             last_s = -1;
         }
         for (int k0 = 0; k0 < n; k0 += 64) {
+            if (share) {
+                // a barrier of every move lies between a flag's write (block
+                // blk - 1) and its reads here, and the next write to the same
+                // flag (block blk + 1)
+                const uint32_t blk = (uint32_t)it * nblk + (uint32_t)(k0 >> 6);
+                const int mine = blk > 0 ? __builtin_amdgcn_readfirstlane(prio[(blk & 1u) ^ 1u]) : 0;
+                if (mine)
+                    __builtin_amdgcn_s_setprio(1);
+                else
+                    __builtin_amdgcn_s_setprio(0);
+                if (tid == 0)
+                    prio[blk & 1u] = share_turn(p.share_tag, wid, blk, cu, mine);
+            }
             // lane l draws the random numbers of micro-step k0 + l; the atom's
             // label becomes its LDS slot
             int bs;
@@ -728,13 +769,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     __shared__ double red[2][NT / 64][2];
     __shared__ double rsl[2];
     __shared__ double ebuf[NT / 64 * 4];
+    __shared__ int prio[2];
     const int w = blockIdx.x;
     const size_t n = (size_t)p.n;
     sweep_walker<T, NT, ROWS, HIST>(p, p.wid_base + (uint32_t)w, coords + (size_t)w * 3 * n, accs + w,
                                     rows_hbm ? rows_hbm + (size_t)w * n : nullptr,
                                     HIST ? p.gr + (size_t)w * (size_t)p.gr_bins : nullptr,
                                     p.trace ? p.trace + (size_t)w * (size_t)p.trace_cap * 6 : nullptr, sweep0, nsw,
-                                    mstart, m, smem_raw, red, rsl, ebuf);
+                                    mstart, m, smem_raw, red, rsl, ebuf, prio);
 }
 
 // The batched sweep kernel (hevmc_sweep_batch): walker slots of several
@@ -751,6 +793,7 @@ __global__ __launch_bounds__(NT) void k_sweep_batch(BatchArgs b, const int32_t *
     __shared__ double red[2][NT / 64][2];
     __shared__ double rsl[2];
     __shared__ double ebuf[NT / 64 * 4];
+    __shared__ int prio[2];
     const int w = blockIdx.x;
     const int r = map[2 * w];
     if (r < 0 || r >= b.count)
@@ -759,7 +802,7 @@ __global__ __launch_bounds__(NT) void k_sweep_batch(BatchArgs b, const int32_t *
     const size_t n = (size_t)b.k[r].n;
     sweep_walker<T, NT, ROWS>(b.k[r], wid, coords + (size_t)w * 3 * n, accs + w,
                               rows_hbm ? rows_hbm + (size_t)w * n : nullptr, nullptr, nullptr, b.sweep0[r], nsw,
-                              b.mstart[r], b.m[r], smem_raw, red, rsl, ebuf);
+                              b.mstart[r], b.m[r], smem_raw, red, rsl, ebuf, prio);
 }
 
 // One wave per walker, kWalkersPerGroup walkers per workgroup (small N): the
@@ -782,7 +825,8 @@ __global__ __launch_bounds__(64 * kWalkersPerGroup) __attribute__((amdgpu_waves_
                                     rows_hbm ? rows_hbm + (size_t)w * n : nullptr,
                                     HIST ? p.gr + (size_t)w * (size_t)p.gr_bins : nullptr,
                                     p.trace ? p.trace + (size_t)w * (size_t)p.trace_cap * 6 : nullptr, sweep0, nsw,
-                                    mstart, m, smem_raw + (size_t)wv * walker_lds, nullptr, nullptr, nullptr);
+                                    mstart, m, smem_raw + (size_t)wv * walker_lds, nullptr, nullptr, nullptr,
+                                    nullptr);
 }
 
 template <typename T, bool ROWS>
@@ -802,7 +846,8 @@ __global__ __launch_bounds__(64 * kWalkersPerGroup) __attribute__((amdgpu_waves_
     const size_t n = (size_t)b.k[r].n;
     sweep_walker<T, 64, ROWS>(b.k[r], wid, coords + (size_t)w * 3 * n, accs + w,
                               rows_hbm ? rows_hbm + (size_t)w * n : nullptr, nullptr, nullptr, b.sweep0[r], nsw,
-                              b.mstart[r], b.m[r], smem_raw + (size_t)wv * walker_lds, nullptr, nullptr, nullptr);
+                              b.mstart[r], b.m[r], smem_raw + (size_t)wv * walker_lds, nullptr, nullptr, nullptr,
+                              nullptr);
 }
 
 // Pair distribution histograms of the W configurations (hevmc_pair_histogram):
