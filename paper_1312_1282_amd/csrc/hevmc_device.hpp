@@ -113,9 +113,26 @@ __device__ __forceinline__ double wrap_box(double y, double L, double invL)
     return (x < 0.0) ? x + L : x;
 }
 
-// Minimum image of one coordinate difference (Sec. 5.1).
+// Minimum image of one coordinate difference (Sec. 5.1), signed (the local
+// energy's gradient needs the direction).
 __device__ __forceinline__ double min_image(double d, const KParams &p) { return d - p.L * rint(d * p.invL); }
 __device__ __forceinline__ float min_image(float d, const KParams &p) { return d - p.Lf * rintf(d * p.invLf); }
+
+// Length of the minimum image of d = a - b for coordinates a, b in [0, L): the
+// shorter of |d| and L - |d|.  For |d| >= L/2, L - |d| is exact (Sterbenz), so
+// the result equals the signed form's magnitude wherever that form rounds
+// d / L away from 1/2, and it takes three instructions instead of four.  Used
+// where only squares of the components matter.
+__device__ __forceinline__ double image_len(double d, const KParams &p)
+{
+    const double a = fabs(d);
+    return fmin(a, p.L - a);
+}
+__device__ __forceinline__ float image_len(float d, const KParams &p)
+{
+    const float a = fabsf(d);
+    return fminf(a, p.Lf - a);
+}
 
 // --------------------------------------------------------------------------
 // FP64 elementary functions for the pair loop.  Division, sqrt and exp from the

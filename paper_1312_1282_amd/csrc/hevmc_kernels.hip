@@ -223,9 +223,9 @@ __device__ void row_pass(const KParams &p, const T *sx, const T *sy, const T *sz
         const T xi = sx[i], yi = sy[i], zi = sz[i];
         double ui = 0.0;
         for (int j = 0; j < n; ++j) {
-            const T dx = min_image(xi - sx[j], p);
-            const T dy = min_image(yi - sy[j], p);
-            const T dz = min_image(zi - sz[j], p);
+            const T dx = image_len(xi - sx[j], p);
+            const T dy = image_len(yi - sy[j], p);
+            const T dz = image_len(zi - sz[j], p);
             const T r2 = dx * dx + dy * dy + dz * dz;
             const T u = pair_u_ri(p, r2, inv_sqrt(r2));
             ui += (j == i) ? 0.0 : (double)u;
@@ -244,8 +244,8 @@ __device__ __forceinline__ void move_partial(const KParams &p, const T *sx, cons
     const int n = p.n;
     for (int i = walker_tid<NT>(); i < n; i += NT) {
         const T xi = sx[i], yi = sy[i], zi = sz[i];
-        const T ax = min_image(ox - xi, p), ay = min_image(oy - yi, p), az_ = min_image(oz - zi, p);
-        const T bx = min_image(nx - xi, p), by = min_image(ny - yi, p), bz = min_image(nz - zi, p);
+        const T ax = image_len(ox - xi, p), ay = image_len(oy - yi, p), az_ = image_len(oz - zi, p);
+        const T bx = image_len(nx - xi, p), by = image_len(ny - yi, p), bz = image_len(nz - zi, p);
         const T r2o = ax * ax + ay * ay + az_ * az_;
         const T r2n = bx * bx + by * by + bz * bz;
         T uo, vo, un, vn;
@@ -260,7 +260,7 @@ __device__ __forceinline__ void move_partial(const KParams &p, const T *sx, cons
 template <typename T>
 __device__ __forceinline__ T dist2(const KParams &p, T ax, T ay, T az_, T bx, T by, T bz)
 {
-    const T dx = min_image(ax - bx, p), dy = min_image(ay - by, p), dz = min_image(az_ - bz, p);
+    const T dx = image_len(ax - bx, p), dy = image_len(ay - by, p), dz = image_len(az_ - bz, p);
     return dx * dx + dy * dy + dz * dz;
 }
 
@@ -516,10 +516,10 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                 const T nz = (T)wrap_box((double)oz + dz, p.L, p.invL);
                 const bool owner = (tid == s % NT);
                 if constexpr (ROWS) {
-                    // forward half: u at the new position only; r^2 is kept for
-                    // the potential if the move is accepted
+                    // forward half: u at the new position only; r^2 and 1/r are
+                    // kept for the potential if the move is accepted
                     double su = 0.0;
-                    T un_[kRowsPerLane], r2n_[kRowsPerLane];
+                    T un_[kRowsPerLane], r2n_[kRowsPerLane], rin_[kRowsPerLane];
                     // FULL: every lane owns kRowsPerLane atoms, so the unrolled
                     // body has no per-lane branch and its loads issue up front
                     auto forward = [&](auto mode_c) {
@@ -544,6 +544,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                             }
                             un_[jj] = uu;
                             r2n_[jj] = r2;
+                            rin_[jj] = ri;
                             su += (double)uu;
                         }
                     };
@@ -610,7 +611,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                                     const T rio = inv_sqrt(r2o);
                                     const T uo = pair_u_ri(p, r2o, rio);
                                     const T vo = pair_v_ri(p, r2o, rio);
-                                    const T vn = pair_v_ri(p, r2n_[jj], inv_sqrt(r2n_[jj]));
+                                    const T vn = pair_v_ri(p, r2n_[jj], rin_[jj]);
                                     const bool other = live && (i != s);
                                     const double dr = other ? (double)un_[jj] - (double)uo : 0.0;
                                     if (live)
