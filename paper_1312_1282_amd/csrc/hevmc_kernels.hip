@@ -461,6 +461,27 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                           : nchunks <= 2       ? 2
                           : nchunks <= 4       ? 4
                                                : 0;
+    // Register copies of the lane's own atoms (FULL lanes of multi-wave row-sum
+    // walkers): atom tid + jj NT's coordinates and row.  Only this thread ever
+    // writes them in LDS between re-sorts and samples (it owns the atoms), so
+    // the copies are refilled from LDS after each of those and kept in step
+    // with every write in between; the pair passes then read no LDS.
+    constexpr bool kCache = ROWS && NT >= 128 && sizeof(T) == 4;
+    constexpr bool kCacheRow = kCache;
+    const bool cached = kCache && lane_mode == kRowsPerLane;
+    T cx[kRowsPerLane], cy[kRowsPerLane], cz[kRowsPerLane];
+    double cr[kRowsPerLane];
+    auto refill = [&]() {
+#pragma unroll
+        for (int jj = 0; jj < kRowsPerLane; ++jj) {
+            const int i = tid + jj * NT;
+            cx[jj] = sx[i];
+            cy[jj] = sy[i];
+            cz[jj] = sz[i];
+            if constexpr (kCacheRow)
+                cr[jj] = ru[i];
+        }
+    };
     int last_s = -1;          // atom accepted in the previous micro-update
     T lx = 0, ly = 0, lz = 0; // its new position (LDS copy not yet visible to all waves)
     double dv_pend = 0.0;     // ROWS: lane partial of dV of the last accepted move
@@ -477,6 +498,8 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
             walker_resort<T, NT, ROWS>(p, sx, sy, sz, ru, key, slot_of);
             last_s = -1;
         }
+        if (kCache && cached && (sorted || it == 0))
+            refill();
         for (int k0 = 0; k0 < n; k0 += 64) {
             if (share) {
                 // a barrier of every move lies between a flag's write (block
@@ -535,6 +558,10 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                                     ri = inv_sqrt(r2);
                                     uu = pair_u_in(p, r2, ri, i != s);
                                 }
+                            } else if constexpr (kCache && MODE == kRowsPerLane) {
+                                r2 = dist2(p, nx, ny, nz, cx[jj], cy[jj], cz[jj]);
+                                ri = inv_sqrt(r2);
+                                uu = pair_u_in(p, r2, ri, i != s);
                             } else {
                                 const bool live = MODE == kRowsPerLane || i < n;
                                 const int ic = MODE == kRowsPerLane ? i : min(i, n - 1);
@@ -607,15 +634,21 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                                 const bool live = MODE == kRowsPerLane || i < n;
                                 if (MODE != 0 || live) {
                                     const int ic = (MODE == 0 || MODE == kRowsPerLane) ? i : min(i, n - 1);
-                                    const T r2o = dist2(p, ox, oy, oz, sx[ic], sy[ic], sz[ic]);
+                                    constexpr bool kReg = kCache && MODE == kRowsPerLane;
+                                    const T r2o = kReg ? dist2(p, ox, oy, oz, cx[jj], cy[jj], cz[jj])
+                                                       : dist2(p, ox, oy, oz, sx[ic], sy[ic], sz[ic]);
                                     const T rio = inv_sqrt(r2o);
                                     const T uo = pair_u_ri(p, r2o, rio);
                                     const T vo = pair_v_ri(p, r2o, rio);
                                     const T vn = pair_v_ri(p, r2n_[jj], rin_[jj]);
                                     const bool other = live && (i != s);
                                     const double dr = other ? (double)un_[jj] - (double)uo : 0.0;
-                                    if (live)
+                                    if constexpr (kReg && kCacheRow) {
+                                        cr[jj] += dr;
+                                        ru[i] = cr[jj];
+                                    } else if (live) {
                                         ru[i] += dr;
+                                    }
                                     dvl += other ? (double)vn - (double)vo : 0.0;
                                 }
                             }
@@ -638,6 +671,16 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                         if (owner) {
                             sx[s] = nx; sy[s] = ny; sz[s] = nz;
                             ru[s] = SU;
+                            if (kCache && cached) {
+                                const int js = s / NT;
+#pragma unroll
+                                for (int jj = 0; jj < kRowsPerLane; ++jj)
+                                    if (jj == js) {
+                                        cx[jj] = nx; cy[jj] = ny; cz[jj] = nz;
+                                        if constexpr (kCacheRow)
+                                            cr[jj] = SU;
+                                    }
+                            }
                         }
                         last_s = s;
                         lx = nx; ly = ny; lz = nz;
@@ -699,6 +742,8 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                 walker_sync<NT>();
                 double el[6];
                 local_energy_pass<T, NT, HIST>(p, sx, sy, sz, ebuf, el, ROWS ? ru : nullptr, hist, nb);
+                if (kCache && cached)
+                    refill();   // the pass rewrote this thread's rows
                 if constexpr (HIST) {
                     walker_sync<NT>();
                     for (int b = tid; b < nb; b += NT)

@@ -111,6 +111,45 @@ def _launch_and_check_samples(wl, picks, sweeps, threads=0, variant=abi.VARIANT_
     return a
 
 
+@pytest.mark.parametrize("n,threads", [(1024, 128), (2048, 256), (2048, 512)])
+def test_fp32_running_totals_follow_the_moves(n, threads):
+    """Sweeps with no sample, so u_run and v_run are the initial sums plus every
+    accepted move's dU and dV.  The FP32 pair value of a pair is the same from
+    either atom and until one of them moves, so the running totals telescope to
+    the FP32 sums over the final configuration: each is within the static
+    tolerance of the oracle's U and V there.  A stale copy of any atom's
+    position or row in any pass would break the telescoping by a whole pair
+    term (covers the register copies of the dense-lane passes, N = 8 x threads,
+    and the LDS passes, N = 4 x threads)."""
+    W, sweeps = 3, 3
+    p = abi.make_params(n, W, precision=abi.FP32, threads=threads, variant=abi.VARIANT_ROWS, density=RHO, b=B,
+                        step_sigma=STEP, seed=11)
+    coords, acc = abi.alloc_state(p)
+    rows = abi.alloc_rows(p)
+    abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
+    abi.sweep(p, coords, acc, 0, 1, abi.NO_MEASURE, 0, rows=rows)
+    abi.sweep(p, coords, acc, 1, sweeps - 1, abi.NO_MEASURE, 0, rows=rows)
+    torch.cuda.synchronize()
+    a = abi.acc_to_numpy(acc)
+    assert np.all(a["n_samples"] == 0)
+    x = coords.cpu().numpy()
+    s_ = osys32(n, seed=11)
+    res = {}
+
+    def work(w):
+        res[w] = O.local_energy(s_, x[w].astype(np.float64))
+
+    th = [threading.Thread(target=work, args=(w,)) for w in range(W)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for w in range(W):
+        ref, scale = res[w]
+        assert within(a["u_run"][w], ref[5], scale, 2e-6), (w, a["u_run"][w], ref[5], scale)
+        assert within(a["v_run"][w], ref[1], scale, 1e-5), (w, a["v_run"][w], ref[1], scale)
+
+
 def test_fp32_n2048_w1024_launch_sampled_walkers():
     wl = configs.C3_N2048_FP32
     a = _launch_and_check_samples(wl, [0, 511, 1023], 5)
