@@ -200,25 +200,32 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L, int32_t gr_bin
                     need_plain * per_group, max_dyn);
     const bool rows_ok = p->n <= kRowsPerLane * threads &&
                          per_group * ((need_rows + align16) & ~align16) <= max_dyn;
-    if (p->variant == HEVMC_VARIANT_ROWS && !rows_ok)
+    // rows that do not fit in LDS can live in registers (FP32, 512 threads,
+    // up to kRegChunks atoms per lane); the walker then needs the plain LDS
+    const bool rreg_ok = !rows_ok && rreg_form(fp32, threads) && p->n <= kRegChunks * threads;
+    if (p->variant == HEVMC_VARIANT_ROWS && !rows_ok && !rreg_ok)
         return fail(HEVMC_ENOFIT, "row-sum sweep needs N <= %d x threads and %zu B of LDS per walker",
                     kRowsPerLane, need_rows);
-    const bool use_rows = p->variant == HEVMC_VARIANT_ROWS || (p->variant == HEVMC_VARIANT_AUTO && rows_ok);
+    const bool use_rows = p->variant == HEVMC_VARIANT_ROWS ||
+                          (p->variant == HEVMC_VARIANT_AUTO && (rows_ok || rreg_ok));
+    const bool rreg = use_rows && !rows_ok;
+    const SweepAttrs attr_use = rreg ? sweep_attrs(fp32, threads, true, true) : use_rows ? attr_rows : attr_plain;
     // workgroups a compute unit can hold: by LDS, and by waves (4 SIMDs, register
     // file shared by the waves of a SIMD)
     const int waves_per_group = threads / 64 * per_group;
-    const int by_waves = 4 * waves_per_simd((use_rows ? attr_rows : attr_plain).vgprs) / waves_per_group;
+    const int by_waves = 4 * waves_per_simd(attr_use.vgprs) / waves_per_group;
     const int groups = (p->n_walkers + per_group - 1) / per_group;
     const int per_cu = (groups + d.cus - 1) / d.cus;
     // spatial order of the atoms (a resort per sweep; it lets whole waves skip
     // the short-range exponentials): used when it costs no workgroups per
     // compute unit.  The choice depends on (N, precision, threads, variant)
     // only, never on the launch's size, so a walker's results do not either.
-    const size_t base_need = ((use_rows ? need_rows : need_plain) + align16) & ~align16;
+    const bool lds_rows = use_rows && !rreg;
+    const size_t base_need = ((lds_rows ? need_rows : need_plain) + align16) & ~align16;
     bool sorted = false;
     if (!wave_mode && p->n <= kRowsPerLane * threads && p->n <= 65535) {
         const size_t tsz = fp32 ? sizeof(float) : sizeof(double);
-        const size_t with_sort = (sorted_walker_lds(p->n, tsz, use_rows) + align16) & ~align16;
+        const size_t with_sort = (sorted_walker_lds(p->n, tsz, lds_rows) + align16) & ~align16;
         auto fit = [&](size_t bytes) {
             const int g = bytes > max_dyn ? 0 : (int)(d.lds_per_cu / (bytes * per_group + stat));
             return by_waves > 0 ? std::min(g, by_waves) : g;
@@ -231,9 +238,9 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L, int32_t gr_bin
     const size_t tsz_w = fp32 ? sizeof(float) : sizeof(double);
     const size_t walker_need =
         gr_bins > 0
-            ? (hist_lds_offset(p->n, tsz_w, use_rows, sorted) + (size_t)gr_bins * sizeof(uint32_t) + align16) &
+            ? (hist_lds_offset(p->n, tsz_w, lds_rows, sorted) + (size_t)gr_bins * sizeof(uint32_t) + align16) &
                   ~align16
-        : sorted ? (sorted_walker_lds(p->n, tsz_w, use_rows) + align16) & ~align16
+        : sorted ? (sorted_walker_lds(p->n, tsz_w, lds_rows) + align16) & ~align16
                  : base_need;
     if (walker_need * per_group > max_dyn)
         return fail(HEVMC_ENOFIT, "walker of %d atoms with a %d-bin pair histogram needs %zu B of LDS; "
@@ -259,6 +266,7 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L, int32_t gr_bin
     L.threads = threads;
     L.fp32 = p->precision == HEVMC_FP32;
     L.rows = use_rows;
+    L.rreg = rreg;
     L.lds_bytes = lds;
     L.walker_lds = walker_need;
     L.stream = (hipStream_t)stream;
@@ -488,6 +496,12 @@ extern "C" hevmc_status hevmc_sweep_batch(int32_t n_requests, const hevmc_reques
     hevmc_status st = plan(&shape, stream, L);
     if (st != HEVMC_OK)
         return st;
+    // the batched kernels keep rows in LDS or not at all: a walker whose rows
+    // would need registers runs the plain sweep here (same LDS layout)
+    if (L.rreg) {
+        L.rows = false;
+        L.rreg = false;
+    }
     if (n_sweeps == 0)
         return HEVMC_OK;
     // every slot of the launch runs n_sweeps sweeps of the same N, so their

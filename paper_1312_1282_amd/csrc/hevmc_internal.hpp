@@ -13,6 +13,8 @@ namespace hevmc {
 // Atoms per lane the row-sum variant of the sweep supports (its forward terms
 // are kept in registers): N <= kRowsPerLane * threads.
 constexpr int kRowsPerLane = 8;
+// Atoms per lane whose rows the rows-in-registers sweep can hold.
+constexpr int kRegChunks = 22;
 
 // Walkers per workgroup of the one-wave-per-walker sweep (threads = 64).
 constexpr int kWalkersPerGroup = 4;
@@ -80,6 +82,7 @@ struct Launch {
     int threads;        // threads per walker workgroup
     bool fp32;
     bool rows;          // row-sum variant of the sweep
+    bool rreg;          // its rows in registers (walkers whose rows do not fit in LDS)
     size_t lds_bytes;   // dynamic LDS per workgroup of the sweep kernel
     size_t walker_lds;  // dynamic LDS of one walker (the per-walker kernels)
     hipStream_t stream;
@@ -103,6 +106,8 @@ struct SweepAttrs {
     int vgprs;
     int static_lds;
 };
-SweepAttrs sweep_attrs(bool fp32, int threads, bool rows);
+SweepAttrs sweep_attrs(bool fp32, int threads, bool rows, bool rreg = false);
+// Whether (precision, threads) has the rows-in-registers sweep.
+bool rreg_form(bool fp32, int threads);
 
 }  // namespace hevmc

@@ -215,22 +215,58 @@ __device__ void local_energy_pass(const KParams &p, const T *sx, const T *sy, co
 }
 
 // Row sums rows[i] = sum_{j != i} u(r_ij) of the lane's atoms.
+// Row sum R_i = sum over j != i of u(r_ij), from the coordinates in LDS.
+template <typename T>
+__device__ double row_of(const KParams &p, const T *sx, const T *sy, const T *sz, int i)
+{
+    const int n = p.n;
+    const T xi = sx[i], yi = sy[i], zi = sz[i];
+    double ui = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const T dx = image_len(xi - sx[j], p);
+        const T dy = image_len(yi - sy[j], p);
+        const T dz = image_len(zi - sz[j], p);
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        const T u = pair_u_ri(p, r2, inv_sqrt(r2));
+        ui += (j == i) ? 0.0 : (double)u;
+    }
+    return ui;
+}
+
 template <typename T, int NT>
 __device__ void row_pass(const KParams &p, const T *sx, const T *sy, const T *sz, double *rows)
 {
-    const int n = p.n;
-    for (int i = walker_tid<NT>(); i < n; i += NT) {
-        const T xi = sx[i], yi = sy[i], zi = sz[i];
-        double ui = 0.0;
-        for (int j = 0; j < n; ++j) {
-            const T dx = image_len(xi - sx[j], p);
-            const T dy = image_len(yi - sy[j], p);
-            const T dz = image_len(zi - sz[j], p);
-            const T r2 = dx * dx + dy * dy + dz * dz;
-            const T u = pair_u_ri(p, r2, inv_sqrt(r2));
-            ui += (j == i) ? 0.0 : (double)u;
+    for (int i = walker_tid<NT>(); i < p.n; i += NT)
+        rows[i] = row_of(p, sx, sy, sz, i);
+}
+
+// Element q of a register array, q wave-uniform: a chain of uniform branches
+// (the empty volatile asm keeps each one a branch rather than a select), so
+// one element moves instead of every element being selected over.
+template <int Q, int K>
+__device__ __forceinline__ double reg_get(const double (&a)[K], int q)
+{
+    if constexpr (Q == K) {
+        return 0.0;
+    } else {
+        if (q == Q) {
+            asm volatile("");
+            return a[Q];
         }
-        rows[i] = ui;
+        return reg_get<Q + 1, K>(a, q);
+    }
+}
+
+template <int Q, int K>
+__device__ __forceinline__ void reg_set(double (&a)[K], int q, double v)
+{
+    if constexpr (Q < K) {
+        if (q == Q) {
+            asm volatile("");
+            a[Q] = v;
+            return;
+        }
+        reg_set<Q + 1, K>(a, q, v);
     }
 }
 
@@ -382,7 +418,21 @@ __device__ __forceinline__ int share_turn(uint32_t tag, uint32_t wid, uint32_t b
     return prev;
 }
 
-template <typename T, int NT, bool ROWS, bool HIST = false>
+// Rows in registers (RREG): the row-sum sweep for walkers whose rows do not
+// fit in LDS beside the coordinates (N = 10976 in FP32 takes 131.7 KB of
+// coordinates; its rows would need 87.8 KB more).  Lane tid keeps the rows of
+// its atoms tid + q NT, q < kRegChunks, in registers; they are loaded from and
+// stored to the HBM rows buffer at the launch's ends, and the moved atom's row
+// reaches the other lanes through the same LDS slot as in the LDS form.  The
+// passes read each partner's coordinates from LDS and keep no per-pair terms
+// between the forward and the accept pass (they are recomputed, bitwise the
+// same), so the registers go to the rows.
+// (kRegChunks: hevmc_internal.hpp)
+// the (precision, threads) instantiated with rows in registers
+template <typename T, int NT>
+constexpr bool kRregForm = std::is_same<T, float>::value && NT == 512;
+
+template <typename T, int NT, bool ROWS, bool HIST = false, bool RREG = false>
 __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *__restrict__ g,
                                              hevmc_walker_acc *__restrict__ accp, double *__restrict__ rg,
                                              uint64_t *__restrict__ grw, double *__restrict__ trw,
@@ -398,8 +448,10 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
     const int tid = walker_tid<NT>(), lane = tid & 63, wave = tid >> 6;
     // spatial order (p.sorted): LDS slot q holds the atom labelled key[q] & 0xFFFF
     const bool sorted = NT > 64 && p.sorted != 0;
-    uint32_t *key = reinterpret_cast<uint32_t *>(smem_raw + sort_lds_offset(n, sizeof(T), ROWS));
-    uint16_t *slot_of = reinterpret_cast<uint16_t *>(smem_raw + slot_of_lds_offset(n, sizeof(T), ROWS));
+    static_assert(!RREG || ROWS, "rows in registers is a form of the row-sum sweep");
+    constexpr bool LROWS = ROWS && !RREG;   // rows in LDS
+    uint32_t *key = reinterpret_cast<uint32_t *>(smem_raw + sort_lds_offset(n, sizeof(T), LROWS));
+    uint16_t *slot_of = reinterpret_cast<uint16_t *>(smem_raw + slot_of_lds_offset(n, sizeof(T), LROWS));
     if (sorted) {
         for (int q = tid; q < n; q += NT) {
             key[q] = (uint32_t)q;
@@ -409,7 +461,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
     // pair histogram of the samples (grw: this walker's [gr_bins] counts)
     const int nb = HIST ? p.gr_bins : 0;
     uint32_t *hist =
-        HIST ? reinterpret_cast<uint32_t *>(smem_raw + hist_lds_offset(n, sizeof(T), ROWS, sorted)) : nullptr;
+        HIST ? reinterpret_cast<uint32_t *>(smem_raw + hist_lds_offset(n, sizeof(T), LROWS, sorted)) : nullptr;
 
     bool bad = false;
     for (int i = tid; i < 3 * n; i += NT) {
@@ -427,7 +479,33 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
     // caller detects
     const bool bad_walker = walker_any<NT>(bad, ebuf);
     int64_t n_acc = 0, n_try = 0, n_samp = 0, n_swm = 0;
-    if constexpr (ROWS) {
+    const int nch_all = (n + NT - 1) / NT;
+    double rr[RREG ? kRegChunks : 1];
+    if constexpr (RREG) {
+        // rows from HBM if they agree with u_run (the same sum rule), else
+        // recomputed; atoms past N in the last chunk hold zero
+        bool valid = false;
+        if (rg) {
+            double c[2] = {0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < kRegChunks; ++q) {
+                const int i = tid + q * NT;
+                rr[q] = (q < nch_all && i < n) ? rg[i] : 0.0;
+                c[0] += rr[q];
+                c[1] += fabs(rr[q]);
+            }
+            block_sum<NT, 2>(c, ebuf);
+            valid = fabs(0.5 * c[0] - u_run) <= 1e-9 * (0.5 * c[1] + 1.0);
+        }
+        walker_sync<NT>();
+        if (!valid) {
+#pragma unroll
+            for (int q = 0; q < kRegChunks; ++q) {
+                const int i = tid + q * NT;
+                rr[q] = (q < nch_all && i < n) ? row_of(p, sx, sy, sz, i) : 0.0;
+            }
+        }
+    } else if constexpr (ROWS) {
         bool valid = false;
         if (rg) {
             double c[2] = {0.0, 0.0};
@@ -495,7 +573,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
         const uint32_t t = sweep0 + (uint32_t)it;
         const bool measured = t >= mstart;
         if (sorted) {
-            walker_resort<T, NT, ROWS>(p, sx, sy, sz, ru, key, slot_of);
+            walker_resort<T, NT, LROWS>(p, sx, sy, sz, ru, key, slot_of);
             last_s = -1;
         }
         if (kCache && cached && (sorted || it == 0))
@@ -538,7 +616,77 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                 const T ny = (T)wrap_box((double)oy + dy, p.L, p.invL);
                 const T nz = (T)wrap_box((double)oz + dz, p.L, p.invL);
                 const bool owner = (tid == s % NT);
-                if constexpr (ROWS) {
+                if constexpr (RREG) {
+                    // forward half: u at the new position, chunk by chunk (the
+                    // last chunk's lanes past N re-read atom N-1 and count nothing)
+                    double su = 0.0;
+#pragma unroll 2
+                    for (int i = tid; i < n; i += NT) {
+                        const T r2 = dist2(p, nx, ny, nz, sx[i], sy[i], sz[i]);
+                        su += (double)pair_u_in(p, r2, inv_sqrt(r2), i != s);
+                    }
+                    const double w0 = wave_sum(su);
+                    const double w1 = (last_s >= 0) ? wave_sum(dv_pend) : 0.0;
+                    const int js = s / NT;
+                    const double rs_own = reg_get<0, kRegChunks>(rr, js);
+                    double SU = 0.0, DVP = 0.0;
+                    if (lane == 0) {
+                        red[k & 1][wave][0] = w0;
+                        red[k & 1][wave][1] = w1;
+                    }
+                    if (owner)
+                        rsl[k & 1] = rs_own;
+                    __syncthreads();
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) {
+                        SU += red[k & 1][q][0];
+                        DVP += red[k & 1][q][1];
+                    }
+                    const double RS = rsl[k & 1];
+                    v_run += DVP;
+                    dv_pend = 0.0;
+                    const double DU = SU - RS;
+                    const bool accept = metropolis_accept_log(DU, lxi);
+                    if (measured) {
+                        n_try += 1;
+                        n_acc += accept ? 1 : 0;
+                    }
+                    if (accept) {
+                        u_run += DU;
+                        // old- and new-position terms (the new ones recomputed
+                        // from the same operands as the forward half): rows, dV
+                        double dvl = 0.0;
+#pragma unroll
+                        for (int q = 0; q < kRegChunks; ++q) {
+                            if (q < nch_all) {
+                                // keeps the next chunk's loads from being hoisted
+                                // over this one (their registers would spill)
+                                asm volatile("" ::: "memory");
+                                const int i = tid + q * NT;
+                                const bool live = i < n;
+                                const int ic = live ? i : n - 1;
+                                const T xi = sx[ic], yi = sy[ic], zi = sz[ic];
+                                const T r2o = dist2(p, ox, oy, oz, xi, yi, zi);
+                                const T r2n = dist2(p, nx, ny, nz, xi, yi, zi);
+                                const T rio = inv_sqrt(r2o), rin = inv_sqrt(r2n);
+                                const T uo = pair_u_ri(p, r2o, rio), un = pair_u_ri(p, r2n, rin);
+                                const T vo = pair_v_ri(p, r2o, rio), vn = pair_v_ri(p, r2n, rin);
+                                const bool other = live && i != s;
+                                rr[q] += other ? (double)un - (double)uo : 0.0;
+                                dvl += other ? (double)vn - (double)vo : 0.0;
+                            }
+                        }
+                        dv_pend = dvl;
+                        if (owner) {
+                            sx[s] = nx; sy[s] = ny; sz[s] = nz;
+                            reg_set<0, kRegChunks>(rr, js, SU);
+                        }
+                        last_s = s;
+                        lx = nx; ly = ny; lz = nz;
+                    } else {
+                        last_s = -1;
+                    }
+                } else if constexpr (ROWS) {
                     // forward half: u at the new position only; r^2 and 1/r are
                     // kept for the potential if the move is accepted
                     double su = 0.0;
@@ -741,7 +889,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                         hist[b] = 0u;
                 walker_sync<NT>();
                 double el[6];
-                local_energy_pass<T, NT, HIST>(p, sx, sy, sz, ebuf, el, ROWS ? ru : nullptr, hist, nb);
+                local_energy_pass<T, NT, HIST>(p, sx, sy, sz, ebuf, el, LROWS ? ru : nullptr, hist, nb);
                 if (kCache && cached)
                     refill();   // the pass rewrote this thread's rows
                 if constexpr (HIST) {
@@ -781,13 +929,22 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
             g[l] = sx[q];
             g[n + l] = sy[q];
             g[2 * n + l] = sz[q];
-            if (ROWS && rg)
+            if (LROWS && rg)
                 rg[l] = ru[q];
         }
     } else {
         for (int i = tid; i < 3 * n; i += NT)
             g[i] = sx[i];
-        if constexpr (ROWS) {
+        if constexpr (RREG) {
+            if (rg) {
+#pragma unroll
+                for (int q = 0; q < kRegChunks; ++q) {
+                    const int i = tid + q * NT;
+                    if (q < nch_all && i < n)
+                        rg[i] = rr[q];
+                }
+            }
+        } else if constexpr (ROWS) {
             if (rg)
                 for (int i = tid; i < n; i += NT)
                     rg[i] = ru[i];
@@ -805,7 +962,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
 
 // The sweep kernel (hevmc_sweep; HIST: hevmc_sweep_gr).  Grid: one workgroup of
 // NT threads per walker.
-template <typename T, int NT, bool ROWS, bool HIST>
+template <typename T, int NT, bool ROWS, bool HIST, bool RREG = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_sweep(KParams p, T *__restrict__ coords,
                                               hevmc_walker_acc *__restrict__ accs,
                                               double *__restrict__ rows_hbm, uint32_t sweep0, int32_t nsw,
@@ -818,11 +975,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     __shared__ int prio[2];
     const int w = blockIdx.x;
     const size_t n = (size_t)p.n;
-    sweep_walker<T, NT, ROWS, HIST>(p, p.wid_base + (uint32_t)w, coords + (size_t)w * 3 * n, accs + w,
-                                    rows_hbm ? rows_hbm + (size_t)w * n : nullptr,
-                                    HIST ? p.gr + (size_t)w * (size_t)p.gr_bins : nullptr,
-                                    p.trace ? p.trace + (size_t)w * (size_t)p.trace_cap * 6 : nullptr, sweep0, nsw,
-                                    mstart, m, smem_raw, red, rsl, ebuf, prio);
+    sweep_walker<T, NT, ROWS, HIST, RREG>(p, p.wid_base + (uint32_t)w, coords + (size_t)w * 3 * n, accs + w,
+                                          rows_hbm ? rows_hbm + (size_t)w * n : nullptr,
+                                          HIST ? p.gr + (size_t)w * (size_t)p.gr_bins : nullptr,
+                                          p.trace ? p.trace + (size_t)w * (size_t)p.trace_cap * 6 : nullptr,
+                                          sweep0, nsw, mstart, m, smem_raw, red, rsl, ebuf, prio);
 }
 
 // The batched sweep kernel (hevmc_sweep_batch): walker slots of several
@@ -1052,7 +1209,7 @@ static hipError_t allow_lds(K kern, size_t bytes)
     return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <typename T, int NT, bool ROWS, bool HIST>
+template <typename T, int NT, bool ROWS, bool HIST, bool RREG = false>
 static hipError_t launch_sweep_v(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows,
                                  uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t m)
 {
@@ -1066,7 +1223,7 @@ static hipError_t launch_sweep_v(const Launch &L, void *coords, hevmc_walker_acc
                            (T *)coords, acc, ROWS ? rows : (double *)nullptr, L.p.n_walkers_grid,
                            (uint32_t)L.walker_lds, sweep0, nsw, mstart, m);
     } else {
-        auto kern = k_sweep<T, NT, ROWS, HIST>;
+        auto kern = k_sweep<T, NT, ROWS, HIST, RREG>;
         hipError_t e = allow_lds(kern, L.lds_bytes);
         if (e != hipSuccess)
             return e;
@@ -1081,6 +1238,12 @@ static hipError_t launch_sweep_t(const Launch &L, void *coords, hevmc_walker_acc
                                  uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t m)
 {
     const bool hist = L.k.gr != nullptr && L.k.gr_bins > 0;
+    if (L.rreg) {
+        if constexpr (kRregForm<T, NT>)
+            return hist ? launch_sweep_v<T, NT, true, true, true>(L, coords, acc, rows, sweep0, nsw, mstart, m)
+                        : launch_sweep_v<T, NT, true, false, true>(L, coords, acc, rows, sweep0, nsw, mstart, m);
+        return hipErrorInvalidValue;
+    }
     if (L.rows)
         return hist ? launch_sweep_v<T, NT, true, true>(L, coords, acc, rows, sweep0, nsw, mstart, m)
                     : launch_sweep_v<T, NT, true, false>(L, coords, acc, rows, sweep0, nsw, mstart, m);
@@ -1204,32 +1367,38 @@ static hipError_t launch_delta_t(const Launch &L, const void *coords, const int3
     } while (0)
 
 template <typename T, int NT>
-static const void *sweep_fn(bool rows)
+static const void *sweep_fn(bool rows, bool rreg)
 {
+    if constexpr (kRregForm<T, NT>)
+        if (rreg)
+            return (const void *)k_sweep<T, NT, true, false, true>;
     return rows ? (const void *)k_sweep<T, NT, true, false> : (const void *)k_sweep<T, NT, false, false>;
 }
 
 // Registers per thread and static LDS of the sweep kernel a launch would use
 // (zeros if unknown).
-static SweepAttrs sweep_attrs_query(bool fp32, int threads, bool rows);
+static SweepAttrs sweep_attrs_query(bool fp32, int threads, bool rows, bool rreg);
 
-SweepAttrs sweep_attrs(bool fp32, int threads, bool rows)
+SweepAttrs sweep_attrs(bool fp32, int threads, bool rows, bool rreg)
 {
-    // kernel attributes do not change: query each (precision, threads, variant) once
-    static std::atomic<int> vgprs[2][6][2], lds[2][6][2];
-    static std::atomic<bool> have[2][6][2];
+    // kernel attributes do not change: query each (precision, threads, form) once
+    static std::atomic<int> vgprs[2][6][3], lds[2][6][3];
+    static std::atomic<bool> have[2][6][3];
     const int t = threads == 64 ? 0 : threads == 128 ? 1 : threads == 256 ? 2 : threads == 512 ? 3 : threads == 1024 ? 4 : 5;
-    if (have[fp32][t][rows].load(std::memory_order_acquire))
-        return SweepAttrs{vgprs[fp32][t][rows].load(std::memory_order_relaxed),
-                          lds[fp32][t][rows].load(std::memory_order_relaxed)};
-    const SweepAttrs a = sweep_attrs_query(fp32, threads, rows);
-    vgprs[fp32][t][rows].store(a.vgprs, std::memory_order_relaxed);
-    lds[fp32][t][rows].store(a.static_lds, std::memory_order_relaxed);
-    have[fp32][t][rows].store(true, std::memory_order_release);
+    const int v = rreg ? 2 : rows ? 1 : 0;
+    if (have[fp32][t][v].load(std::memory_order_acquire))
+        return SweepAttrs{vgprs[fp32][t][v].load(std::memory_order_relaxed),
+                          lds[fp32][t][v].load(std::memory_order_relaxed)};
+    const SweepAttrs a = sweep_attrs_query(fp32, threads, rows, rreg);
+    vgprs[fp32][t][v].store(a.vgprs, std::memory_order_relaxed);
+    lds[fp32][t][v].store(a.static_lds, std::memory_order_relaxed);
+    have[fp32][t][v].store(true, std::memory_order_release);
     return a;
 }
 
-static SweepAttrs sweep_attrs_query(bool fp32, int threads, bool rows)
+bool rreg_form(bool fp32, int threads) { return fp32 ? kRregForm<float, 512> && threads == 512 : false; }
+
+static SweepAttrs sweep_attrs_query(bool fp32, int threads, bool rows, bool rreg)
 {
     const void *f = nullptr;
     switch (threads) {
@@ -1238,10 +1407,10 @@ static SweepAttrs sweep_attrs_query(bool fp32, int threads, bool rows)
                  : (rows ? (const void *)k_sweep_wave<double, true, false>
                          : (const void *)k_sweep_wave<double, false, false>);
         break;
-    case 128: f = fp32 ? sweep_fn<float, 128>(rows) : sweep_fn<double, 128>(rows); break;
-    case 256: f = fp32 ? sweep_fn<float, 256>(rows) : sweep_fn<double, 256>(rows); break;
-    case 512: f = fp32 ? sweep_fn<float, 512>(rows) : sweep_fn<double, 512>(rows); break;
-    case 1024: f = fp32 ? sweep_fn<float, 1024>(rows) : sweep_fn<double, 1024>(rows); break;
+    case 128: f = fp32 ? sweep_fn<float, 128>(rows, rreg) : sweep_fn<double, 128>(rows, rreg); break;
+    case 256: f = fp32 ? sweep_fn<float, 256>(rows, rreg) : sweep_fn<double, 256>(rows, rreg); break;
+    case 512: f = fp32 ? sweep_fn<float, 512>(rows, rreg) : sweep_fn<double, 512>(rows, rreg); break;
+    case 1024: f = fp32 ? sweep_fn<float, 1024>(rows, rreg) : sweep_fn<double, 1024>(rows, rreg); break;
     default: return SweepAttrs{0, 0};
     }
     hipFuncAttributes a;

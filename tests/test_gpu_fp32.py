@@ -111,7 +111,7 @@ def _launch_and_check_samples(wl, picks, sweeps, threads=0, variant=abi.VARIANT_
     return a
 
 
-@pytest.mark.parametrize("n,threads", [(1024, 128), (2048, 256), (2048, 512)])
+@pytest.mark.parametrize("n,threads", [(1024, 128), (2048, 256), (2048, 512), (8192, 512), (10976, 512)])
 def test_fp32_running_totals_follow_the_moves(n, threads):
     """Sweeps with no sample, so u_run and v_run are the initial sums plus every
     accepted move's dU and dV.  The FP32 pair value of a pair is the same from
@@ -120,8 +120,9 @@ def test_fp32_running_totals_follow_the_moves(n, threads):
     tolerance of the oracle's U and V there.  A stale copy of any atom's
     position or row in any pass would break the telescoping by a whole pair
     term (covers the register copies of the dense-lane passes, N = 8 x threads,
-    and the LDS passes, N = 4 x threads)."""
-    W, sweeps = 3, 3
+    the LDS passes, N = 4 x threads, and the rows kept in registers because
+    they do not fit in LDS, N = 8192 and 10976 at 512 threads)."""
+    W, sweeps = (3, 3) if n <= 2048 else (2, 2)
     p = abi.make_params(n, W, precision=abi.FP32, threads=threads, variant=abi.VARIANT_ROWS, density=RHO, b=B,
                         step_sigma=STEP, seed=11)
     coords, acc = abi.alloc_state(p)

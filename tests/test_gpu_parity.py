@@ -468,13 +468,16 @@ def test_non_finite_state_is_reported(threads):
 @pytest.mark.parametrize("wl,threads,variant,spatial", [
     (configs.C2_N2048_FP64, 256, abi.VARIANT_ROWS, 1),
     (configs.C3_N2048_FP32, 256, abi.VARIANT_ROWS, 1),
-    (configs.C5_N10976_FP32, 512, abi.VARIANT_PLAIN, 0),
+    (configs.C5_N10976_FP32, 512, abi.VARIANT_ROWS, 0),
     (configs.C1_SMALL_FP64, 64, abi.VARIANT_ROWS, 0),
 ])
 def test_launch_plans_of_the_workloads(wl, threads, variant, spatial):
-    """The plans the parity and bench runs rely on: row sums where they fit,
+    """The plans the parity and bench runs rely on: row sums where they fit
+    (in registers for N = 10976 FP32, whose LDS holds only the coordinates),
     spatial order where it costs no residency, one wave per small walker."""
     plan = abi.plan_launch(abi.params_for(wl))
     assert (plan["threads"], plan["variant"], plan["spatial_order"]) == (threads, variant, spatial), plan
     assert plan["walkers_per_cu"] >= 1 and plan["lds_per_group"] >= plan["lds_per_walker"]
+    if wl is configs.C5_N10976_FP32:
+        assert plan["lds_per_walker"] == 3 * 4 * wl.n
 
