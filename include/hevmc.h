@@ -68,7 +68,11 @@ typedef enum {
  * R_i = sum_{j != i} u(r_ij) (FP64, in LDS; refreshed by every local-energy
  * pass) and evaluates only u at the new position per trial move; the old
  * position's terms, the row updates and dV are formed only for accepted moves.
- * ROWS needs N <= 8 x threads and 8 N more bytes of LDS per walker. */
+ * ROWS needs N <= 8 x threads and 8 N more bytes of LDS per walker; in FP32
+ * with 512 threads and N <= 22 x 512 it can instead keep the rows in
+ * registers (no LDS beyond the coordinates, no refresh at local-energy passes;
+ * the rows persist through the rows buffer as in LDS form).  The batched sweep
+ * runs such walkers PLAIN. */
 typedef enum {
     HEVMC_VARIANT_AUTO = 0,      /* ROWS when it fits, else PLAIN */
     HEVMC_VARIANT_PLAIN = 1,
