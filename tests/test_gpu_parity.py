@@ -481,3 +481,24 @@ def test_launch_plans_of_the_workloads(wl, threads, variant, spatial):
     if wl is configs.C5_N10976_FP32:
         assert plan["lds_per_walker"] == 3 * 4 * wl.n
 
+
+
+@pytest.mark.parametrize("wl", [configs.C2_N2048_FP64, configs.C3_N2048_FP32])
+def test_walkers_do_not_depend_on_compute_unit_sharing(wl):
+    """In the full launch two walkers share each compute unit and trade issue
+    priority by progress; launched four at a time, a walker has a compute unit
+    to itself.  Scheduling is all that differs: walkers 0-3 leave both launches
+    with the same bits."""
+    out = []
+    for W in (wl.walkers, 4):
+        p = abi.params_for(wl, n_walkers=W)
+        assert abi.plan_launch(p)["walkers_per_cu"] == (2 if W == wl.walkers else 1)
+        coords, acc = abi.alloc_state(p)
+        rows = abi.alloc_rows(p)
+        abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
+        abi.sweep(p, coords, acc, 0, 2, 0, 2, rows=rows)
+        torch.cuda.synchronize()
+        out.append((coords[:4].cpu().numpy(), abi.acc_to_numpy(acc)[:4], rows[:4].cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1].tobytes() == out[1][1].tobytes()
+    assert np.array_equal(out[0][2], out[1][2])
