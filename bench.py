@@ -306,7 +306,10 @@ def cpu_baseline(wl, sweeps):
         "kind": "oracle",
         "sample": f"{W} walkers x {sweeps} sweeps of N={wl.n} with a local energy every {m} sweeps, "
                   f"one walker per thread, {dt:.1f} s wall",
+        "pair_terms_per_s": moves * (wl.n - 1) / dt,
         "single_core_moves_per_s": wl.n * s1 / dt1,
+        "single_core_pair_terms_per_s": wl.n * s1 * (wl.n - 1) / dt1,
+        "single_core_sample": f"1 walker x {s1} sweeps, one thread, {dt1:.1f} s",
     }
 
 
@@ -437,6 +440,7 @@ def main():
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, args.cpu_sweeps)
         cb["gpu_over_cpu"] = value / cb["value"]
+        cb["gpu_over_single_core"] = value / cb["single_core_moves_per_s"]
         line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
 
