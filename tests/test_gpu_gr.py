@@ -148,3 +148,30 @@ def test_sweep_histogram_n2048_w512_sampled_walkers():
         t.join()
     for w in (0, 511):
         _assert_counts(got[w], res[w][2], res[w][3])
+
+
+def test_sweep_histogram_with_rows_in_registers():
+    """N = 10976 in FP32 keeps its row sums in registers.  A launch whose only
+    sample is its last sweep histograms the final configuration: the counts
+    equal the oracle's histogram of the returned coordinates (FP32 distances,
+    edge slack), and the chain has the same bits without the histogram."""
+    n, W, nb, sweeps = 10976, 2, 100, 2
+    p = abi.make_params(n, W, precision=abi.FP32, threads=512, density=RHO, b=B, step_sigma=STEP, seed=7)
+    plan = abi.plan_launch(p)
+    assert plan["variant"] == abi.VARIANT_ROWS and plan["lds_per_walker"] == 3 * 4 * n
+    runs = {}
+    for with_gr in (False, True):
+        coords, acc = abi.alloc_state(p)
+        rows = abi.alloc_rows(p)
+        abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
+        gr = torch.zeros((W, nb), dtype=torch.int64, device="cuda") if with_gr else None
+        abi.sweep(p, coords, acc, 0, sweeps, 0, sweeps, rows=rows, gr=gr)
+        torch.cuda.synchronize()
+        runs[with_gr] = (coords.cpu().numpy(), abi.acc_to_numpy(acc), None if gr is None else gr.cpu().numpy())
+    assert np.array_equal(runs[False][0], runs[True][0])
+    assert runs[False][1].tobytes() == runs[True][1].tobytes()
+    x, got = runs[True][0], runs[True][2]
+    s_ = osys(n, fp32=True)
+    for w in range(W):
+        ref, edge = O.pair_histogram(s_, x[w].astype(np.float64), nb, rel_window=2e-6)
+        _assert_counts(got[w], ref, edge)
