@@ -431,6 +431,8 @@ def main():
             "traffic_unit": "bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
             "kernel": "k_sweep",
             "launch_ms_avg": float(launch_ms.mean()),
+            "launch_ms_median": float(np.median(launch_ms)),
+            "launch_ms_min_max": [float(launch_ms.min()), float(launch_ms.max())],
             "flop_per_launch": flop_launch,
             "flop_per_pair_term": FLOP_PER_PAIR_TERM,
             "pair_terms_per_launch": pair_terms_launch,
