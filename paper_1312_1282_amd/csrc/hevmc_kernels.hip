@@ -617,8 +617,8 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                 const T nz = (T)wrap_box((double)oz + dz, p.L, p.invL);
                 const bool owner = (tid == s % NT);
                 if constexpr (RREG) {
-                    // forward half: u at the new position, chunk by chunk (the
-                    // last chunk's lanes past N re-read atom N-1 and count nothing)
+                    // forward half: u at the new position over the lane's atoms
+                    // (the rows are not touched, so this loop needs no unrolling)
                     double su = 0.0;
 #pragma unroll 2
                     for (int i = tid; i < n; i += NT) {
