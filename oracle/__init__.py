@@ -25,6 +25,7 @@ class System(C.Structure):
         ("hbar2_over_m", C.c_double),
         ("step_sigma", C.c_double),
         ("seed", C.c_uint64),
+        ("fp32_coords", C.c_int32),
     ]
 
 
@@ -83,6 +84,10 @@ def lib():
         L.or_walker_init.argtypes = [sp, dp, wp]
         L.or_run_walker.argtypes = [sp, C.c_uint32, dp, wp, C.c_uint32, C.c_int32, C.c_uint32,
                                     C.c_int32, dp, C.POINTER(C.c_int64)]
+        L.or_metropolis_accept.argtypes = [C.c_double, C.c_double]
+        L.or_metropolis_accept.restype = C.c_int
+        L.or_run_walker_log.argtypes = [sp, C.c_uint32, dp, wp, C.c_uint32, C.c_int32, C.c_uint32,
+                                        C.c_int32, dp, C.c_int64]
         L.or_run_walkers.argtypes = [sp, C.c_uint32, C.c_int32, dp, wp, C.c_uint32, C.c_int32,
                                      C.c_uint32, C.c_int32, C.c_int32]
         _lib = L
@@ -100,8 +105,11 @@ def _f64(a, shape=None):
     return a
 
 
-def system(n, L, b, hbar2_over_m=12.1194, step_sigma=1.0, seed=1, order=0):
-    return System(int(n), int(order), float(L), float(b), float(hbar2_over_m), float(step_sigma), int(seed))
+def system(n, L, b, hbar2_over_m=12.1194, step_sigma=1.0, seed=1, order=0, fp32_coords=False):
+    """fp32_coords: keep every stored position rounded to FP32 (the precision
+    form's coordinates; use box_side(..., fp32=True) for L)."""
+    return System(int(n), int(order), float(L), float(b), float(hbar2_over_m), float(step_sigma), int(seed),
+                  int(bool(fp32_coords)))
 
 
 def box_side(n, density, fp32=False):
@@ -226,6 +234,27 @@ def run_walker(sys_, w, xyz, acc, t0, n_sweeps, measure_start, m, record_el=Fals
     lib().or_run_walker(C.byref(sys_), int(w), _dp(xyz), C.byref(acc), int(t0), int(n_sweeps),
                         int(measure_start), int(m), _dp(el) if record_el else None, C.byref(n_el))
     return el[: n_el.value] if record_el else None
+
+
+def metropolis_accept(du, xi):
+    """Eq. (5) decision for a move with Eq. (7) sum du and uniform xi."""
+    return bool(lib().or_metropolis_accept(float(du), float(xi)))
+
+
+MOVE_LOG_FIELDS = ("s", "accepted", "du", "dv", "scale_u", "scale_v")
+
+
+def run_walker_log(sys_, w, xyz, acc, t0, n_sweeps, measure_start, m, cap=None):
+    """run_walker that returns the record of every micro-update, an array of
+    shape (moves, 6): (s, accepted, dU, dV, scale_u, scale_v), dU and dV the
+    Eq. (7) sums at the configuration each move was proposed in."""
+    if xyz.dtype != np.float64 or not xyz.flags.c_contiguous or xyz.shape != (3, sys_.n):
+        raise ValueError("xyz must be a C-contiguous float64 (3, N) array")
+    cap = n_sweeps * sys_.n if cap is None else cap
+    log = np.zeros((cap, 6))
+    lib().or_run_walker_log(C.byref(sys_), int(w), _dp(xyz), C.byref(acc), int(t0), int(n_sweeps),
+                            int(measure_start), int(m), _dp(log), int(cap))
+    return log
 
 
 def run_walkers(sys_, w0, xyz, accs, t0, n_sweeps, measure_start, m, n_threads):

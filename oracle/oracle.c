@@ -217,6 +217,18 @@ void or_totals(const or_system *sys, const double *xyz, double *U, double *V)
     *V = sv + cv;
 }
 
+/* How a position in [0, L) is kept.  FP64: as it is.  Reading (precision
+ * form, FP32 coordinates with FP64 arithmetic on them): rounded to the nearest
+ * FP32 number; the side L is then itself an FP32 number (or_box_side with
+ * fp32), and a value that rounds up to L is the same point as 0, kept as 0. */
+static double stored_coord(const or_system *sys, double x)
+{
+    if (!sys->fp32_coords)
+        return x;
+    const double f = (double)(float)x;
+    return f >= sys->L ? 0.0 : f;
+}
+
 /* Sec. 2: X' = X with r_s -> r_s + delta; the moved atom is put back into the
  * primary box [0, L) (periodic boundary conditions, Sec. 5.1):
  * x' = y - L floor(y / L) with y = x + delta, and x' = x' - L if rounding left
@@ -230,7 +242,7 @@ void or_trial_position(const or_system *sys, const double *xyz, int32_t s,
         double x = y - L * floor(y / L);
         if (x >= L)
             x -= L;
-        rnew[a] = x;
+        rnew[a] = stored_coord(sys, x);
     }
 }
 
@@ -391,7 +403,7 @@ void or_fcc_start(const or_system *sys, uint32_t w, double *xyz)
         or_philox4x32_10(ctr, key, r);
         for (int c = 0; c < 3; ++c) {
             double x = a * ((double)idx[c] + basis[beta][c] + 0.25);
-            xyz[c * n + p] = x + 1e-3 * a * (unit32(r[c]) - 0.5);
+            xyz[c * n + p] = stored_coord(sys, x + 1e-3 * a * (unit32(r[c]) - 0.5));
         }
     }
 }
@@ -402,13 +414,20 @@ void or_walker_init(const or_system *sys, const double *xyz, or_walker *acc)
     or_totals(sys, xyz, &acc->u_run, &acc->v_run);
 }
 
+/* Eq. (5): accept the trial configuration if the ratio of the squared
+ * wavefunctions, exp(2 dU) by Eq. (7), exceeds the uniform xi (strict ">"). */
+int or_metropolis_accept(double du, double xi)
+{
+    return exp(2.0 * du) > xi;
+}
+
 /* Sec. 5.1 workflow for one walker (one Markov chain): N micro-updates per
  * sweep ("macroupdate", Sec. 4.1); each draws s, xi, delta, forms dU by Eq. (7),
  * accepts by Eq. (5) (strict ">"), and on acceptance moves r_s.  Analysis
- * (local energy) every m sweeps (Sec. 4.1). */
-int or_run_walker(const or_system *sys, uint32_t w, double *xyz, or_walker *acc,
-                  uint32_t t0, int32_t n_sweeps, uint32_t measure_start, int32_t m,
-                  double *el_out, int64_t *n_el)
+ * (local energy) every m sweeps (Sec. 4.1).  log: see or_run_walker_log. */
+static int run_walker(const or_system *sys, uint32_t w, double *xyz, or_walker *acc,
+                      uint32_t t0, int32_t n_sweeps, uint32_t measure_start, int32_t m,
+                      double *el_out, int64_t *n_el, double *log, int64_t log_cap)
 {
     const int n = sys->n;
     for (int32_t it = 0; it < n_sweeps; ++it) {
@@ -416,11 +435,21 @@ int or_run_walker(const or_system *sys, uint32_t w, double *xyz, or_walker *acc,
         const int measured = t >= measure_start;
         for (int k = 0; k < n; ++k) {
             int32_t s;
-            double xi, delta[3], rnew[3], du, dv;
+            double xi, delta[3], rnew[3], du, dv, scu, scv;
             or_draw_move(sys, (uint32_t)k, t, w, &s, &xi, delta);
             or_trial_position(sys, xyz, s, delta, rnew);
-            or_delta(sys, xyz, s, rnew, &du, &dv, NULL, NULL);
-            int accept = exp(2.0 * du) > xi;
+            or_delta(sys, xyz, s, rnew, &du, &dv, &scu, &scv);
+            int accept = or_metropolis_accept(du, xi);
+            const int64_t q = (int64_t)it * n + k;
+            if (log && q < log_cap) {
+                double *rec = log + 6 * q;
+                rec[0] = (double)s;
+                rec[1] = (double)accept;
+                rec[2] = du;
+                rec[3] = dv;
+                rec[4] = scu;
+                rec[5] = scv;
+            }
             if (measured) {
                 acc->n_try += 1;
                 acc->n_acc += accept;
@@ -455,6 +484,20 @@ int or_run_walker(const or_system *sys, uint32_t w, double *xyz, or_walker *acc,
         acc->n_sweeps_meas += 1;
     }
     return 0;
+}
+
+int or_run_walker(const or_system *sys, uint32_t w, double *xyz, or_walker *acc,
+                  uint32_t t0, int32_t n_sweeps, uint32_t measure_start, int32_t m,
+                  double *el_out, int64_t *n_el)
+{
+    return run_walker(sys, w, xyz, acc, t0, n_sweeps, measure_start, m, el_out, n_el, NULL, 0);
+}
+
+int or_run_walker_log(const or_system *sys, uint32_t w, double *xyz, or_walker *acc,
+                      uint32_t t0, int32_t n_sweeps, uint32_t measure_start, int32_t m,
+                      double *log, int64_t log_cap)
+{
+    return run_walker(sys, w, xyz, acc, t0, n_sweeps, measure_start, m, NULL, NULL, log, log_cap);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -33,6 +33,9 @@ typedef struct {
     double hbar2_over_m;   /* hbar^2 / m_He (K Angstrom^2)                         */
     double step_sigma;     /* std. dev. of each Cartesian component of delta (A)   */
     uint64_t seed;         /* Philox key = (low 32 bits, high 32 bits)             */
+    int32_t fp32_coords;   /* 1: every stored position (start, accepted move) is
+                              rounded to the nearest FP32 number, as the precision
+                              form keeps its coordinates; arithmetic stays FP64    */
 } or_system;
 
 /* Per-walker running state and accumulators (all sums Neumaier-compensated;
@@ -75,7 +78,8 @@ double or_min_image(double d, double L);
 /* Totals U = sum_{i<j} u(r_ij) = ln psi (Eq. 6) and V = sum_{i<j} V(r_ij). */
 void or_totals(const or_system *sys, const double *xyz, double *U, double *V);
 
-/* Single-particle trial move r_s -> wrap(r_s + delta): new position. */
+/* Single-particle trial move r_s -> wrap(r_s + delta): new position
+ * (rounded to FP32 if sys->fp32_coords). */
 void or_trial_position(const or_system *sys, const double *xyz, int32_t s,
                        const double delta[3], double rnew[3]);
 
@@ -103,6 +107,10 @@ void or_pair_histogram(const or_system *sys, const double *xyz, int32_t nb, uint
 
 void or_fcc_start(const or_system *sys, uint32_t w, double *xyz);
 
+/* Eq. (5): the Metropolis decision for a move whose Eq. (7) sum is du:
+ * 1 if |psi'|^2 / |psi|^2 = exp(2 du) > xi (strict), else 0. */
+int or_metropolis_accept(double du, double xi);
+
 /* Fresh running state for a configuration: u_run, v_run from or_totals,
  * accumulators zeroed. */
 void or_walker_init(const or_system *sys, const double *xyz, or_walker *acc);
@@ -115,6 +123,14 @@ void or_walker_init(const or_system *sys, const double *xyz, or_walker *acc);
 int or_run_walker(const or_system *sys, uint32_t w, double *xyz, or_walker *acc,
                   uint32_t t0, int32_t n_sweeps, uint32_t measure_start, int32_t m,
                   double *el_out, int64_t *n_el);
+
+/* or_run_walker that also records every micro-update q = (t - t0) N + k of
+ * the call, for q < log_cap: log[6 q .. 6 q + 5] = (s, accepted, dU, dV,
+ * scale_u, scale_v) with the Eq. (7) sums of or_delta at the configuration
+ * the move was proposed in.  The chain itself is the same as or_run_walker's. */
+int or_run_walker_log(const or_system *sys, uint32_t w, double *xyz, or_walker *acc,
+                      uint32_t t0, int32_t n_sweeps, uint32_t measure_start, int32_t m,
+                      double *log, int64_t log_cap);
 
 /* Same as or_run_walker for walkers w0 .. w0+nw-1 (xyz: nw blocks of 3N,
  * acc: nw entries), spread over n_threads POSIX threads, one walker at a time

@@ -179,3 +179,62 @@ def test_paper_sample_run_loose():
     assert abs(e + tail - e_paper) < 0.25, (e + tail, e_paper)
     assert abs(v + tail - v_paper) < 0.5, (v + tail, v_paper)
     assert abs(t - t_paper) < 0.5, (t, t_paper)
+
+
+def _acceptance_probability(du):
+    """Probability over xi uniform in (0, 1) that the oracle's Eq. (5) decision
+    accepts a move with Eq. (7) sum du: the decision is monotone in xi, so this
+    is the threshold where it flips, found by bisection on the decision itself."""
+    if not O.metropolis_accept(du, 0.0):
+        return 0.0
+    if O.metropolis_accept(du, 1.0):
+        return 1.0
+    # bisection over the bit patterns of the doubles in [0, 1] (ordered like
+    # the numbers), so that tiny thresholds are found to the last bit
+    as_f = lambda i: float(np.array([i], dtype=np.int64).view(np.float64)[0])
+    lo, hi = 0, int(np.array([1.0]).view(np.int64)[0])
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        lo, hi = (mid, hi) if O.metropolis_accept(du, as_f(mid)) else (lo, mid)
+    return as_f(hi)
+
+
+def test_detailed_balance_four_particles():
+    """Eq. (5) with Eq. (7) obeys detailed balance for |psi|^2 of Eq. (6):
+    pi(X) T(X -> X') = pi(X') T(X' -> X) for 10^4 random (X, s, delta) at N=4,
+    with pi = exp(2U) from the brute-force total U, T = (1/N) g(delta) A, the
+    proposal symmetric (s uniform, g Gaussian in each component, the reverse
+    move is -delta from X', which the wrap must bring back to X) and A the
+    acceptance probability of the oracle's own decision.  Compared in log
+    form to 1e-12 relative.  A decision on exp(dU) (sampling |psi|), a sign
+    or index slip in dU, or a wrap that is not reversible breaks it."""
+    L, n = 12.0, 4
+    s_ = O.system(n, L, B, hbar2_over_m=HB, step_sigma=1.5, seed=3)
+    rng = np.random.default_rng(2024)
+    checked = wrapped = partial = 0
+    for case in range(10000):
+        x = np.ascontiguousarray(rng.uniform(0.0, L, size=(3, n)))
+        s = int(rng.integers(0, n))
+        sigma = 1.5 if case % 4 else 0.45 * L   # every fourth move large enough to wrap
+        d = rng.normal(0.0, sigma, size=3)
+        xn = O.trial_position(s_, x, s, d)
+        wrapped += int(np.any(np.abs(x[:, s] + d - xn) > 1e-9))
+        x2 = x.copy()
+        x2[:, s] = xn
+        back = O.trial_position(s_, x2, s, -d)
+        gap = np.abs(back - x[:, s])
+        gap = np.minimum(gap, L - gap)   # 0 and L are the same point
+        assert np.all(gap < 1e-12 * L), (case, back, x[:, s])
+        U1, _ = O.totals(s_, x)
+        U2, _ = O.totals(s_, x2)
+        du12 = O.delta(s_, x, s, xn)[0]
+        du21 = O.delta(s_, x2, s, x[:, s])[0]
+        a12, a21 = _acceptance_probability(du12), _acceptance_probability(du21)
+        if min(a12, a21) < np.finfo(np.float64).tiny:
+            continue   # a core overlap: exp(2 dU) underflows below the normal doubles
+        partial += int(a12 < 1.0 or a21 < 1.0)
+        lhs = 2.0 * U1 + np.log(a12)
+        rhs = 2.0 * U2 + np.log(a21)
+        assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(2 * U1), abs(2 * U2)), (case, lhs, rhs, du12, du21)
+        checked += 1
+    assert checked > 9000 and wrapped > 1000 and partial > 3000, (checked, wrapped, partial)
