@@ -216,6 +216,25 @@ hevmc_status hevmc_sweep_trace(const hevmc_params *p, void *coords, hevmc_walker
                                double *trace, int32_t trace_cap, uint32_t sweep0, int32_t n_sweeps,
                                uint32_t measure_start, int32_t energy_every, void *stream);
 
+/* ---- Per-move records (parity of the micro-updates) ----------------------- */
+
+/* hevmc_sweep that also records every micro-update of walkers
+ * w = 0 .. log_walkers-1 (the micro-update of Eqs. (5) and (7), Sec. 2):
+ * log[w][q][0..3] = (s, accepted, dU, dV) for the q-th micro-update of the
+ * call, q = (t - sweep0) N + k, for q < log_cap (later ones are not recorded).
+ * s is the moved atom's label (its index in the coordinate arrays), accepted
+ * is 1.0 or 0.0, dU is the Eq. (7) sum the decision used (for the row-sum
+ * forms: sum_i u(|r_s' - r_i|) minus the moved atom's row sum), and dV the
+ * potential change: for every micro-update in the PLAIN form, for accepted
+ * ones only in the row-sum forms (NaN for rejected ones, whose dV those forms
+ * never form).  log: device [log_walkers][log_cap][4] doubles, caller-owned,
+ * written only where recorded.  The sweep's results are bitwise the same with
+ * or without the records.  HEVMC_EINVAL for log = NULL, log_walkers outside
+ * [1, n_walkers] or log_cap < 1. */
+hevmc_status hevmc_sweep_log(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
+                             double *log, int32_t log_walkers, int64_t log_cap, uint32_t sweep0,
+                             int32_t n_sweeps, uint32_t measure_start, int32_t energy_every, void *stream);
+
 /* ---- Batched sweeps (serving: walkers of several requests in one launch) ---- */
 
 #define HEVMC_MAX_BATCH 16

@@ -2,7 +2,8 @@
 
 The computation lives in libhevmc.so (HIP kernels for gfx950 behind the C ABI
 of include/hevmc.h); ``abi`` binds it, ``configs`` holds the synthetic
-workloads and ``stats`` the post-processing of per-walker accumulators.
+workloads, ``observables`` the host post-processing of sampled quantities
+(pair distribution, reweighting in b) and ``serving`` the request server.
 """
 from . import configs  # noqa: F401
 

@@ -89,7 +89,7 @@ class Plan(C.Structure):
 
 EXPORTS = [
     "hevmc_plan_launch", "hevmc_box", "hevmc_footprint", "hevmc_init_walkers", "hevmc_sweep", "hevmc_sweep_gr",
-    "hevmc_pair_histogram", "hevmc_sweep_trace", "hevmc_local_energy",
+    "hevmc_pair_histogram", "hevmc_sweep_trace", "hevmc_sweep_log", "hevmc_local_energy",
     "hevmc_move_delta", "hevmc_draw_moves", "hevmc_sweep_batch", "hevmc_create", "hevmc_create_on", "hevmc_run",
     "hevmc_sync", "hevmc_get_acc", "hevmc_get_coords", "hevmc_get_sweep", "hevmc_destroy",
     "hevmc_eval_config", "hevmc_last_error",
@@ -117,6 +117,8 @@ def lib():
             "hevmc_sweep_gr": [P, vp, vp, vp, vp, C.c_int32, C.c_uint32, C.c_int32, C.c_uint32, C.c_int32, vp],
             "hevmc_pair_histogram": [P, vp, C.c_int32, vp, vp],
             "hevmc_sweep_trace": [P, vp, vp, vp, vp, C.c_int32, C.c_uint32, C.c_int32, C.c_uint32, C.c_int32, vp],
+            "hevmc_sweep_log": [P, vp, vp, vp, vp, C.c_int32, C.c_int64, C.c_uint32, C.c_int32, C.c_uint32,
+                                C.c_int32, vp],
             "hevmc_local_energy": [P, vp, vp, vp],
             "hevmc_move_delta": [P, vp, vp, vp, vp, vp],
             "hevmc_draw_moves": [P, C.c_uint32, vp, vp, vp, vp],
@@ -243,14 +245,22 @@ def init_walkers(p, coords, acc, fcc_start=True, stream=None, rows=None):
 
 
 def sweep(p, coords, acc, sweep0, n_sweeps, measure_start=NO_MEASURE, energy_every=0, stream=None, rows=None,
-          gr=None, trace=None):
+          gr=None, trace=None, movelog=None):
     """hevmc_sweep; hevmc_sweep_gr when gr (int64 [W][bins], device) is given;
-    hevmc_sweep_trace when trace (float64 [W][cap][6], device) is given."""
+    hevmc_sweep_trace when trace (float64 [W][cap][6], device) is given;
+    hevmc_sweep_log when movelog (float64 [log_walkers][cap][4], device) is
+    given (records (s, accepted, dU, dV) of every micro-update of the first
+    log_walkers walkers)."""
     cp = _ptr(coords, coord_dtype(p), (p.n_walkers, 3, p.n), "coords")
     ap = _ptr(acc, None, (p.n_walkers, ACC_BYTES), "acc")
-    if gr is not None and trace is not None:
-        raise ValueError("one of gr and trace per call")
-    if trace is not None:
+    if sum(x is not None for x in (gr, trace, movelog)) > 1:
+        raise ValueError("one of gr, trace and movelog per call")
+    if movelog is not None:
+        lw, cap = int(movelog.shape[0]), int(movelog.shape[1])
+        lp = _ptr(movelog, _torch().float64, (lw, cap, 4), "movelog")
+        _check(lib().hevmc_sweep_log(C.byref(p), cp, ap, _rows_ptr(p, rows), lp, lw, cap, int(sweep0),
+                                     int(n_sweeps), int(measure_start), int(energy_every), _stream(stream)))
+    elif trace is not None:
         cap = int(trace.shape[1])
         tp = _ptr(trace, _torch().float64, (p.n_walkers, cap, 6), "trace")
         _check(lib().hevmc_sweep_trace(C.byref(p), cp, ap, _rows_ptr(p, rows), tp, cap, int(sweep0),

@@ -303,6 +303,9 @@ void make_kparams(const hevmc_params *p, KParams &k)
     k.trace = nullptr;
     k.trace_cap = 0;
     k.share_tag = 0;
+    k.movelog = nullptr;
+    k.log_cap = 0;
+    k.log_walkers = 0;
 }
 
 // A fresh nonzero 24-bit tag per sweep launch: walkers compare progress only
@@ -403,10 +406,19 @@ static bool shares_cu(const Launch &L)
     return d.lds_per_cu / (L.lds_bytes + static_lds(L.threads)) >= 2;
 }
 
-// The sweep with its optional outputs: pair histogram and per-sample trace.
+// Optional per-move records of a sweep (hevmc_sweep_log).
+struct MoveLog {
+    double *log = nullptr;
+    int32_t walkers = 0;
+    int64_t cap = 0;
+};
+
+// The sweep with its optional outputs: pair histogram, per-sample trace and
+// per-move records.
 static hevmc_status sweep_with(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
                                uint64_t *gr, int32_t gr_bins, double *trace, int32_t trace_cap, uint32_t sweep0,
-                               int32_t n_sweeps, uint32_t measure_start, int32_t energy_every, void *stream)
+                               int32_t n_sweeps, uint32_t measure_start, int32_t energy_every, void *stream,
+                               const MoveLog &mlog = MoveLog())
 {
     if (gr && (gr_bins < 1 || gr_bins > HEVMC_MAX_GR_BINS))
         return fail(HEVMC_EINVAL, "gr_bins = %d must be in [1, %d]", gr_bins, HEVMC_MAX_GR_BINS);
@@ -419,6 +431,15 @@ static hevmc_status sweep_with(const hevmc_params *p, void *coords, hevmc_walker
     L.k.gr = gr;
     L.k.trace = trace;
     L.k.trace_cap = trace ? trace_cap : 0;
+    if (mlog.log) {
+        if (mlog.walkers < 1 || mlog.walkers > p->n_walkers)
+            return fail(HEVMC_EINVAL, "log_walkers = %d must be in [1, n_walkers = %d]", mlog.walkers, p->n_walkers);
+        if (mlog.cap < 1)
+            return fail(HEVMC_EINVAL, "log_cap = %lld must be >= 1", (long long)mlog.cap);
+        L.k.movelog = mlog.log;
+        L.k.log_walkers = mlog.walkers;
+        L.k.log_cap = mlog.cap;
+    }
     if (!coords || !acc)
         return fail(HEVMC_EINVAL, "coords and acc must be device pointers");
     if (n_sweeps < 0)
@@ -456,6 +477,20 @@ extern "C" hevmc_status hevmc_sweep_trace(const hevmc_params *p, void *coords, h
 {
     return sweep_with(p, coords, acc, rows, nullptr, 0, trace, trace_cap, sweep0, n_sweeps, measure_start,
                       energy_every, stream);
+}
+
+extern "C" hevmc_status hevmc_sweep_log(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
+                                        double *log, int32_t log_walkers, int64_t log_cap, uint32_t sweep0,
+                                        int32_t n_sweeps, uint32_t measure_start, int32_t energy_every, void *stream)
+{
+    if (!log)
+        return fail(HEVMC_EINVAL, "log must be a device pointer");
+    MoveLog ml;
+    ml.log = log;
+    ml.walkers = log_walkers;
+    ml.cap = log_cap;
+    return sweep_with(p, coords, acc, rows, nullptr, 0, nullptr, 0, sweep0, n_sweeps, measure_start, energy_every,
+                      stream, ml);
 }
 
 extern "C" hevmc_status hevmc_sweep_batch(int32_t n_requests, const hevmc_request *requests, const int32_t *map,

@@ -32,6 +32,9 @@ struct KParams {
     double *trace;       // [W][trace_cap][6] per-sample local-energy records, or null
     int32_t trace_cap;   // samples per walker the trace holds
     uint32_t share_tag;  // nonzero: this launch's tag for balancing walkers that share a CU (0: off)
+    double *movelog;     // [log_walkers][log_cap][4] per-move records (s, accepted, dU, dV), or null
+    int64_t log_cap;     // records per logged walker
+    int32_t log_walkers; // walkers 0 .. log_walkers-1 of the launch are logged
 };
 
 // HFD-B(HE) pair potential (Aziz, McCourt, Wong 1987), the interaction named
@@ -111,6 +114,24 @@ __device__ __forceinline__ double wrap_box(double y, double L, double invL)
     double x = y - L * floor(y * invL);
     x = (x >= L) ? x - L : x;
     return (x < 0.0) ? x + L : x;
+}
+
+// A wrapped trial coordinate as the walker stores it.  In FP32 a value just
+// below L can round up to L itself, the same point as 0 of the periodic box:
+// it is stored as 0, so every stored coordinate lies in [0, L).
+__device__ __forceinline__ double stored_coord(double y, const KParams &p) { return wrap_box(y, p.L, p.invL); }
+__device__ __forceinline__ float stored_coord_f(double y, const KParams &p)
+{
+    const float v = (float)wrap_box(y, p.L, p.invL);
+    return v >= p.Lf ? 0.0f : v;
+}
+template <typename T>
+__device__ __forceinline__ T trial_coord(double y, const KParams &p)
+{
+    if constexpr (sizeof(T) == 4)
+        return stored_coord_f(y, p);
+    else
+        return stored_coord(y, p);
 }
 
 // Minimum image of one coordinate difference (Sec. 5.1), signed (the local

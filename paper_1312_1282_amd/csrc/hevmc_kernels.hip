@@ -18,9 +18,11 @@
 //    position and dU = sum_i u(|r_s' - r_i|) - R_s.  Only an accepted move needs
 //    the old-position terms: it updates the rows of all atoms and forms dV
 //    (the potential change enters no result for a rejected move).  dV's
-//    workgroup sum rides on the next micro-update's reduction.  The rows are
-//    refreshed exactly by every local-energy pass, can be kept in HBM between
-//    launches, and are checked against u_run (sum_i R_i = 2 U) on load.
+//    workgroup sum rides on the next micro-update's reduction.  Rows kept in
+//    LDS are refreshed exactly by every local-energy pass; rows kept in
+//    registers (walkers whose rows do not fit in LDS) are only updated move by
+//    move within a launch.  Either way they can be kept in HBM between
+//    launches and are checked against u_run (sum_i R_i = 2 U) on load.
 //
 // Walkers of at most 512 atoms can run one wave each, four to a workgroup,
 // synchronised by wavefront fences only.  Larger walkers re-sort their atoms
@@ -394,7 +396,8 @@ __device__ void walker_resort(const KParams &p, T *sx, T *sy, T *sz, double *ru,
 // (T) and, for ROWS, the row sums (double) at rows_lds_offset(n, sizeof(T)).
 // g: the walker's coordinates [3][N]; accp: its accumulators; rg: its row sums
 // in HBM ([N] doubles) or null; grw: its pair histogram ([gr_bins], HIST
-// only); trw: its per-sample records ([trace_cap][6]) or null.  For NT = 64 the walker is one wave and red, rsl, ebuf are not used.
+// only); trw: its per-sample records ([trace_cap][6]) or null; mlw: its
+// per-move records ([log_cap][4]: atom label, accepted, dU, dV) or null.  For NT = 64 the walker is one wave and red, rsl, ebuf are not used.
 // Two walkers that share a compute unit compete for its four SIMDs, and the
 // hardware issues from the oldest ready wave first.  Left to that, the walker
 // dispatched first finishes in about two thirds of the launch and its partner
@@ -436,6 +439,7 @@ template <typename T, int NT, bool ROWS, bool HIST = false, bool RREG = false>
 __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *__restrict__ g,
                                              hevmc_walker_acc *__restrict__ accp, double *__restrict__ rg,
                                              uint64_t *__restrict__ grw, double *__restrict__ trw,
+                                             double *__restrict__ mlw,
                                              uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t m,
                                              unsigned char *smem_raw, double (*red)[NT / 64][2], double *rsl,
                                              double *ebuf, int *prio)
@@ -569,6 +573,12 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
     const bool share = NT > 64 && prio != nullptr && p.share_tag != 0;
     const uint32_t cu = share ? __smid() : 0u;
     const uint32_t nblk = (uint32_t)((n + 63) / 64);
+    // micro-updates done in this launch: picks the reduction buffer, so that
+    // consecutive micro-updates use different buffers across sweep ends too
+    uint32_t mv = 0;
+    // per-move record awaiting its dV (row-sum forms reduce an accepted move's
+    // dV with the next micro-update), or -1
+    int64_t log_pend = -1;
     for (int it = 0; it < nsw; ++it) {
         const uint32_t t = sweep0 + (uint32_t)it;
         const bool measured = t >= mstart;
@@ -598,11 +608,15 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
             double bxi, bdx, bdy, bdz;
             draw_move(p, (uint32_t)(k0 + lane), t, wid, bs, bxi, bdx, bdy, bdz);
             const double blx = log(bxi);   // ln xi of micro-step k0 + lane
+            const int blab = bs;           // the atom's label (bs becomes its slot)
             if (sorted)
                 bs = slot_of[bs];
             const int kend = min(64, n - k0);
             for (int j = 0; j < kend; ++j) {
                 const int k = k0 + j;
+                const uint32_t par = mv & 1u;
+                ++mv;
+                const int64_t q_log = (int64_t)it * n + k;   // this micro-update's record
                 const int s = readlane_i(bs, j);
                 const double lxi = lane_value(blx, j);
                 const double dx = lane_value(bdx, j), dy = lane_value(bdy, j), dz = lane_value(bdz, j);
@@ -612,10 +626,26 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                 } else {
                     ox = sx[s]; oy = sy[s]; oz = sz[s];
                 }
-                const T nx = (T)wrap_box((double)ox + dx, p.L, p.invL);
-                const T ny = (T)wrap_box((double)oy + dy, p.L, p.invL);
-                const T nz = (T)wrap_box((double)oz + dz, p.L, p.invL);
+                const T nx = trial_coord<T>((double)ox + dx, p);
+                const T ny = trial_coord<T>((double)oy + dy, p);
+                const T nz = trial_coord<T>((double)oz + dz, p);
                 const bool owner = (tid == s % NT);
+                // the record of this micro-update (label, decision, dU; dV when known)
+                auto log_move = [&](bool acc_, double du_, double dv_) {
+                    if (mlw && tid == 0 && q_log < p.log_cap) {
+                        double *rec = mlw + 4 * q_log;
+                        rec[0] = (double)readlane_i(blab, j);
+                        rec[1] = acc_ ? 1.0 : 0.0;
+                        rec[2] = du_;
+                        rec[3] = dv_;
+                    }
+                };
+                // the dV of the previous accepted micro-update (row-sum forms)
+                auto log_pending_dv = [&](double dv_) {
+                    if (mlw && tid == 0 && log_pend >= 0)
+                        mlw[4 * log_pend + 3] = dv_;
+                    log_pend = -1;
+                };
                 if constexpr (RREG) {
                     // forward half: u at the new position over the lane's atoms
                     // (the rows are not touched, so this loop needs no unrolling)
@@ -631,22 +661,26 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                     const double rs_own = reg_get<0, kRegChunks>(rr, js);
                     double SU = 0.0, DVP = 0.0;
                     if (lane == 0) {
-                        red[k & 1][wave][0] = w0;
-                        red[k & 1][wave][1] = w1;
+                        red[par][wave][0] = w0;
+                        red[par][wave][1] = w1;
                     }
                     if (owner)
-                        rsl[k & 1] = rs_own;
+                        rsl[par] = rs_own;
                     __syncthreads();
 #pragma unroll
                     for (int q = 0; q < NW; ++q) {
-                        SU += red[k & 1][q][0];
-                        DVP += red[k & 1][q][1];
+                        SU += red[par][q][0];
+                        DVP += red[par][q][1];
                     }
-                    const double RS = rsl[k & 1];
+                    const double RS = rsl[par];
                     v_run += DVP;
                     dv_pend = 0.0;
                     const double DU = SU - RS;
                     const bool accept = metropolis_accept_log(DU, lxi);
+                    log_pending_dv(DVP);
+                    log_move(accept, DU, __builtin_nan(""));
+                    if (accept && q_log < p.log_cap)
+                        log_pend = q_log;
                     if (measured) {
                         n_try += 1;
                         n_acc += accept ? 1 : 0;
@@ -748,23 +782,27 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                         RS = ru[s];
                     } else {
                         if (lane == 0) {
-                            red[k & 1][wave][0] = w0;
-                            red[k & 1][wave][1] = w1;
+                            red[par][wave][0] = w0;
+                            red[par][wave][1] = w1;
                         }
                         if (owner)
-                            rsl[k & 1] = ru[s];
+                            rsl[par] = ru[s];
                         __syncthreads();
 #pragma unroll
                         for (int q = 0; q < NW; ++q) {
-                            SU += red[k & 1][q][0];
-                            DVP += red[k & 1][q][1];
+                            SU += red[par][q][0];
+                            DVP += red[par][q][1];
                         }
-                        RS = rsl[k & 1];
+                        RS = rsl[par];
                     }
                     v_run += DVP;
                     dv_pend = 0.0;
                     const double DU = SU - RS;
                     const bool accept = metropolis_accept_log(DU, lxi);
+                    log_pending_dv(DVP);
+                    log_move(accept, DU, __builtin_nan(""));
+                    if (accept && q_log < p.log_cap)
+                        log_pend = q_log;
                     if (measured) {
                         n_try += 1;
                         n_acc += accept ? 1 : 0;
@@ -846,17 +884,18 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                         DV = dv;
                     } else {
                         if (lane == 0) {
-                            red[k & 1][wave][0] = du;
-                            red[k & 1][wave][1] = dv;
+                            red[par][wave][0] = du;
+                            red[par][wave][1] = dv;
                         }
                         __syncthreads();
 #pragma unroll
                         for (int q = 0; q < NW; ++q) {
-                            DU += red[k & 1][q][0];
-                            DV += red[k & 1][q][1];
+                            DU += red[par][q][0];
+                            DV += red[par][q][1];
                         }
                     }
                     const bool accept = metropolis_accept_log(DU, lxi);
+                    log_move(accept, DU, DV);
                     if (measured) {
                         n_try += 1;
                         n_acc += accept ? 1 : 0;
@@ -881,6 +920,9 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
             block_sum<NT, 1>(f, ebuf);
             v_run += f[0];
             dv_pend = 0.0;
+            if (mlw && tid == 0 && log_pend >= 0)
+                mlw[4 * log_pend + 3] = f[0];
+            log_pend = -1;
         }
         if (measured) {
             if (m > 0 && (t - mstart + 1) % (uint32_t)m == 0) {
@@ -979,6 +1021,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                           rows_hbm ? rows_hbm + (size_t)w * n : nullptr,
                                           HIST ? p.gr + (size_t)w * (size_t)p.gr_bins : nullptr,
                                           p.trace ? p.trace + (size_t)w * (size_t)p.trace_cap * 6 : nullptr,
+                                          (p.movelog && w < p.log_walkers)
+                                              ? p.movelog + (size_t)w * (size_t)p.log_cap * 4
+                                              : nullptr,
                                           sweep0, nsw, mstart, m, smem_raw, red, rsl, ebuf, prio);
 }
 
@@ -1004,8 +1049,8 @@ __global__ __launch_bounds__(NT) void k_sweep_batch(BatchArgs b, const int32_t *
     const uint32_t wid = (uint32_t)map[2 * w + 1];
     const size_t n = (size_t)b.k[r].n;
     sweep_walker<T, NT, ROWS>(b.k[r], wid, coords + (size_t)w * 3 * n, accs + w,
-                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, nullptr, nullptr, b.sweep0[r], nsw,
-                              b.mstart[r], b.m[r], smem_raw, red, rsl, ebuf, prio);
+                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, nullptr, nullptr, nullptr, b.sweep0[r],
+                              nsw, b.mstart[r], b.m[r], smem_raw, red, rsl, ebuf, prio);
 }
 
 // One wave per walker, kWalkersPerGroup walkers per workgroup (small N): the
@@ -1027,9 +1072,12 @@ __global__ __launch_bounds__(64 * kWalkersPerGroup) __attribute__((amdgpu_waves_
     sweep_walker<T, 64, ROWS, HIST>(p, p.wid_base + (uint32_t)w, coords + (size_t)w * 3 * n, accs + w,
                                     rows_hbm ? rows_hbm + (size_t)w * n : nullptr,
                                     HIST ? p.gr + (size_t)w * (size_t)p.gr_bins : nullptr,
-                                    p.trace ? p.trace + (size_t)w * (size_t)p.trace_cap * 6 : nullptr, sweep0, nsw,
-                                    mstart, m, smem_raw + (size_t)wv * walker_lds, nullptr, nullptr, nullptr,
-                                    nullptr);
+                                    p.trace ? p.trace + (size_t)w * (size_t)p.trace_cap * 6 : nullptr,
+                                    (p.movelog && w < p.log_walkers)
+                                        ? p.movelog + (size_t)w * (size_t)p.log_cap * 4
+                                        : nullptr,
+                                    sweep0, nsw, mstart, m, smem_raw + (size_t)wv * walker_lds, nullptr, nullptr,
+                                    nullptr, nullptr);
 }
 
 template <typename T, bool ROWS>
@@ -1048,9 +1096,9 @@ __global__ __launch_bounds__(64 * kWalkersPerGroup) __attribute__((amdgpu_waves_
     const uint32_t wid = (uint32_t)map[2 * w + 1];
     const size_t n = (size_t)b.k[r].n;
     sweep_walker<T, 64, ROWS>(b.k[r], wid, coords + (size_t)w * 3 * n, accs + w,
-                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, nullptr, nullptr, b.sweep0[r], nsw,
-                              b.mstart[r], b.m[r], smem_raw + (size_t)wv * walker_lds, nullptr, nullptr, nullptr,
-                              nullptr);
+                              rows_hbm ? rows_hbm + (size_t)w * n : nullptr, nullptr, nullptr, nullptr, b.sweep0[r],
+                              nsw, b.mstart[r], b.m[r], smem_raw + (size_t)wv * walker_lds, nullptr, nullptr,
+                              nullptr, nullptr);
 }
 
 // Pair distribution histograms of the W configurations (hevmc_pair_histogram):
@@ -1169,9 +1217,9 @@ __global__ __launch_bounds__(NT) void k_move_delta(KParams p, const T *__restric
         return;
     }
     const T ox = sx[s], oy = sx[n + s], oz = sx[2 * n + s];
-    const T nx = (T)wrap_box((double)ox + delta[3 * w + 0], p.L, p.invL);
-    const T ny = (T)wrap_box((double)oy + delta[3 * w + 1], p.L, p.invL);
-    const T nz = (T)wrap_box((double)oz + delta[3 * w + 2], p.L, p.invL);
+    const T nx = trial_coord<T>((double)ox + delta[3 * w + 0], p);
+    const T ny = trial_coord<T>((double)oy + delta[3 * w + 1], p);
+    const T nz = trial_coord<T>((double)oz + delta[3 * w + 2], p);
     double v[2] = {0.0, 0.0};
     move_partial<T, NT>(p, sx, sx + n, sx + 2 * n, s, ox, oy, oz, nx, ny, nz, v[0], v[1]);
     // same reduction order as the plain sweep: wave butterfly, then waves in order

@@ -184,3 +184,41 @@ def test_fp32_chain_against_fp64_chain():
     d = res[abi.FP32] - res[abi.FP64]
     se = d.std(ddof=1) / np.sqrt(W)
     assert abs(d.mean()) <= 3 * se + 1e-9, (d.mean() * KELVIN_TO_MK, se * KELVIN_TO_MK)
+
+
+def test_fp32_form_against_fp64_at_benchmark_size():
+    """The precision-form workload (N=2048, 1024 walkers) in FP32 and in FP64
+    on identical seeds and walker ids, 40 + 60 sweeps with a sample every 5:
+      * the FP32 local energy of every FP64 chain's final configuration
+        (rounded to FP32) is within 1 mK/atom of its FP64 local energy (the
+        form's target; measured ~0.01 mK/atom);
+      * the chain energies per atom agree within 2 combined standard errors
+        (the bar for chains), and within 4 walker-paired ones."""
+    wl = configs.C3_N2048_FP32
+    equil, measured = 40, 60
+    res = {}
+    for prec in (abi.FP64, abi.FP32):
+        p = abi.params_for(wl, precision=prec)
+        coords, acc = abi.alloc_state(p)
+        rows = abi.alloc_rows(p)
+        abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
+        abi.sweep(p, coords, acc, 0, equil, abi.NO_MEASURE, 0, rows=rows)
+        abi.sweep(p, coords, acc, equil, measured, equil, wl.m, rows=rows)
+        torch.cuda.synchronize()
+        a = abi.acc_to_numpy(acc)
+        assert np.all(a["n_samples"] == measured // wl.m)
+        res[prec] = ((a["sum_e"] + a["c_e"]) / a["n_samples"] / wl.n, coords)
+    e64, e32 = res[abi.FP64][0], res[abi.FP32][0]
+    W = wl.walkers
+    se64, se32 = e64.std(ddof=1) / np.sqrt(W), e32.std(ddof=1) / np.sqrt(W)
+    assert abs(e32.mean() - e64.mean()) <= 2 * np.hypot(se64, se32), (e32.mean(), e64.mean(), se64, se32)
+    d = e32 - e64
+    assert abs(d.mean()) <= 4 * d.std(ddof=1) / np.sqrt(W) + 1e-9
+    x32 = res[abi.FP64][1].to(torch.float32)
+    out64 = torch.zeros((W, 6), dtype=torch.float64, device="cuda")
+    out32 = torch.zeros((W, 6), dtype=torch.float64, device="cuda")
+    abi.local_energy(abi.params_for(wl, precision=abi.FP64), x32.to(torch.float64), out64)
+    abi.local_energy(abi.params_for(wl, precision=abi.FP32), x32, out32)
+    torch.cuda.synchronize()
+    err_mk = (out32[:, 0] - out64[:, 0]).abs().cpu().numpy() / wl.n * KELVIN_TO_MK
+    assert err_mk.max() <= 1.0, err_mk.max()
