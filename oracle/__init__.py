@@ -72,11 +72,14 @@ def lib():
         L.or_u_derivs.argtypes = [sp, C.c_double, dp, dp, dp]
         L.or_aziz.argtypes = [C.c_double]
         L.or_aziz.restype = C.c_double
+        L.or_aziz_deriv.argtypes = [C.c_double]
+        L.or_aziz_deriv.restype = C.c_double
         L.or_min_image.argtypes = [C.c_double, C.c_double]
         L.or_min_image.restype = C.c_double
         L.or_totals.argtypes = [sp, dp, dp, dp]
         L.or_trial_position.argtypes = [sp, dp, C.c_int32, dp, dp]
         L.or_delta.argtypes = [sp, dp, C.c_int32, dp, dp, dp, dp, dp]
+        L.or_delta_slopes.argtypes = [sp, dp, C.c_int32, dp, dp, dp]
         L.or_local_energy.argtypes = [sp, dp, dp, dp, dp, dp]
         L.or_fcc_start.argtypes = [sp, C.c_uint32, dp]
         u64p = C.POINTER(C.c_uint64)
@@ -150,6 +153,10 @@ def aziz(r):
     return lib().or_aziz(float(r))
 
 
+def aziz_deriv(r):
+    return lib().or_aziz_deriv(float(r))
+
+
 def min_image(d, L):
     return lib().or_min_image(float(d), float(L))
 
@@ -176,6 +183,16 @@ def delta(sys_, xyz, s, rnew):
     vals = [C.c_double() for _ in range(4)]
     lib().or_delta(C.byref(sys_), _dp(x), int(s), _dp(rn), *[C.byref(v) for v in vals])
     return tuple(v.value for v in vals)
+
+
+def delta_slopes(sys_, xyz, s, rnew):
+    """Tolerance slopes of a move: (sum |u'|, sum |dV/dr|) over the old and
+    the trial distances of atom s to every other atom."""
+    x = _f64(xyz, (3, sys_.n))
+    rn = _f64(rnew, (3,))
+    a, b_ = C.c_double(), C.c_double()
+    lib().or_delta_slopes(C.byref(sys_), _dp(x), int(s), _dp(rn), C.byref(a), C.byref(b_))
+    return a.value, b_.value
 
 
 def local_energy(sys_, xyz, want_derivs=False):
@@ -241,17 +258,18 @@ def metropolis_accept(du, xi):
     return bool(lib().or_metropolis_accept(float(du), float(xi)))
 
 
-MOVE_LOG_FIELDS = ("s", "accepted", "du", "dv", "scale_u", "scale_v")
+MOVE_LOG_FIELDS = ("s", "accepted", "du", "dv", "scale_u", "scale_v", "slope_u", "slope_v")
 
 
 def run_walker_log(sys_, w, xyz, acc, t0, n_sweeps, measure_start, m, cap=None):
     """run_walker that returns the record of every micro-update, an array of
-    shape (moves, 6): (s, accepted, dU, dV, scale_u, scale_v), dU and dV the
-    Eq. (7) sums at the configuration each move was proposed in."""
+    shape (moves, 8): (s, accepted, dU, dV, scale_u, scale_v, slope_u,
+    slope_v), dU and dV the Eq. (7) sums at the configuration each move was
+    proposed in, the slopes those of delta_slopes there."""
     if xyz.dtype != np.float64 or not xyz.flags.c_contiguous or xyz.shape != (3, sys_.n):
         raise ValueError("xyz must be a C-contiguous float64 (3, N) array")
     cap = n_sweeps * sys_.n if cap is None else cap
-    log = np.zeros((cap, 6))
+    log = np.zeros((cap, len(MOVE_LOG_FIELDS)))
     lib().or_run_walker_log(C.byref(sys_), int(w), _dp(xyz), C.byref(acc), int(t0), int(n_sweeps),
                             int(measure_start), int(m), _dp(log), int(cap))
     return log

@@ -170,6 +170,31 @@ double or_aziz(double r)
     return AZ_EPS * (rep - F * disp);
 }
 
+/* dV/dr of the untruncated HFD-B(HE) potential (derivative of or_aziz term
+ * by term, x = r / r_m):
+ *   dV/dr = (eps / r_m) [ A e^{-alpha x + beta x^2} (2 beta x - alpha)
+ *                         - F'(x) P(x) - F(x) P'(x) ],
+ *   P = C6 x^-6 + C8 x^-8 + C10 x^-10,  P' = -6 C6 x^-7 - 8 C8 x^-9 - 10 C10 x^-11,
+ *   F' = 2 (D/x - 1) (D/x^2) F for x < D, else 0.
+ * Used only as a tolerance scale (how far V moves when a pair distance carries
+ * a small absolute error). */
+double or_aziz_deriv(double r)
+{
+    double x = r / AZ_RM;
+    double F = 1.0, dF = 0.0;
+    if (x < AZ_D) {
+        double q = AZ_D / x - 1.0;
+        F = exp(-(q * q));
+        dF = 2.0 * q * (AZ_D / (x * x)) * F;
+    }
+    double x2 = x * x, x6 = x2 * x2 * x2, x7 = x6 * x, x8 = x6 * x2, x9 = x8 * x, x10 = x8 * x2;
+    double x11 = x10 * x;
+    double rep = AZ_A * exp(-AZ_ALPHA * x + AZ_BETA * x2);
+    double P = AZ_C6 / x6 + AZ_C8 / x8 + AZ_C10 / x10;
+    double dP = -6.0 * AZ_C6 / x7 - 8.0 * AZ_C8 / x9 - 10.0 * AZ_C10 / x11;
+    return AZ_EPS / AZ_RM * (rep * (2.0 * AZ_BETA * x - AZ_ALPHA) - dF * P - F * dP);
+}
+
 /* Sec. 5.1: periodic boundary conditions on all interparticle distances.
  * Reading: the minimum image, d - L * nearest_integer(d / L), ties to even. */
 double or_min_image(double d, double L)
@@ -272,6 +297,33 @@ void or_delta(const or_system *sys, const double *xyz, int32_t s, const double r
     *dv = sv + cv;
     if (scale_u) *scale_u = au;
     if (scale_v) *scale_v = av;
+}
+
+/* Slopes of the Eq. (7) terms: slope_u = sum_{i != s} (|u'(r_i')| + |u'(r_i)|),
+ * slope_v the same with dV/dr (zero beyond L/2), r_i' and r_i the distances of
+ * atom i from the trial and the old position.  A tolerance scale: the change
+ * of dU and dV when every pair distance moves by at most one unit (to first
+ * order). */
+void or_delta_slopes(const or_system *sys, const double *xyz, int32_t s, const double rnew[3],
+                     double *slope_u, double *slope_v)
+{
+    const int n = sys->n;
+    const double h = 0.5 * sys->L;
+    double rold[3] = {xyz[s], xyz[n + s], xyz[2 * n + s]};
+    double au = 0, av = 0;
+    for (int i = 0; i < n; ++i) {
+        if (i == s)
+            continue;
+        double r[2] = {point_dist(sys, rnew, xyz, i), point_dist(sys, rold, xyz, i)};
+        for (int c = 0; c < 2; ++c) {
+            double u, du, d2u;
+            or_u_derivs(sys, r[c], &u, &du, &d2u);
+            au += fabs(du);
+            av += r[c] <= h ? fabs(or_aziz_deriv(r[c])) : 0.0;
+        }
+    }
+    *slope_u = au;
+    *slope_v = av;
 }
 
 /* Local energy E_L = H psi / psi (Sec. 2, local value A_L) with the Hamiltonian
@@ -442,13 +494,14 @@ static int run_walker(const or_system *sys, uint32_t w, double *xyz, or_walker *
             int accept = or_metropolis_accept(du, xi);
             const int64_t q = (int64_t)it * n + k;
             if (log && q < log_cap) {
-                double *rec = log + 6 * q;
+                double *rec = log + 8 * q;
                 rec[0] = (double)s;
                 rec[1] = (double)accept;
                 rec[2] = du;
                 rec[3] = dv;
                 rec[4] = scu;
                 rec[5] = scv;
+                or_delta_slopes(sys, xyz, s, rnew, &rec[6], &rec[7]);
             }
             if (measured) {
                 acc->n_try += 1;

@@ -73,6 +73,7 @@ double or_f(const or_system *sys, double r);
 double or_u(const or_system *sys, double r);
 void or_u_derivs(const or_system *sys, double r, double *u, double *du, double *d2u);
 double or_aziz(double r);                          /* untruncated V(r)      */
+double or_aziz_deriv(double r);                    /* its dV/dr             */
 double or_min_image(double d, double L);
 
 /* Totals U = sum_{i<j} u(r_ij) = ln psi (Eq. 6) and V = sum_{i<j} V(r_ij). */
@@ -87,6 +88,11 @@ void or_trial_position(const or_system *sys, const double *xyz, int32_t s,
  * for V.  scale_u / scale_v = sum of |terms| (tolerance scale). */
 void or_delta(const or_system *sys, const double *xyz, int32_t s, const double rnew[3],
               double *du, double *dv, double *scale_u, double *scale_v);
+
+/* Tolerance slopes of the same move: slope_u = sum_{i != s} (|u'(r_i')| +
+ * |u'(r_i)|), slope_v likewise with dV/dr (zero beyond L/2). */
+void or_delta_slopes(const or_system *sys, const double *xyz, int32_t s, const double rnew[3],
+                     double *slope_u, double *slope_v);
 
 /* Local energy of a configuration.  out[0..5] = E_L, V, T_PB, T_JF, T_F, U.
  * scale = sum |V_ij| + kappa * sum_i (|Lap_i| + |G_i|^2).  grad (3N, SoA) and
@@ -125,9 +131,9 @@ int or_run_walker(const or_system *sys, uint32_t w, double *xyz, or_walker *acc,
                   double *el_out, int64_t *n_el);
 
 /* or_run_walker that also records every micro-update q = (t - t0) N + k of
- * the call, for q < log_cap: log[6 q .. 6 q + 5] = (s, accepted, dU, dV,
- * scale_u, scale_v) with the Eq. (7) sums of or_delta at the configuration
- * the move was proposed in.  The chain itself is the same as or_run_walker's. */
+ * the call, for q < log_cap: log[8 q .. 8 q + 7] = (s, accepted, dU, dV,
+ * scale_u, scale_v, slope_u, slope_v) with the Eq. (7) sums of or_delta and
+ * the slopes of or_delta_slopes at the configuration the move was proposed in.  The chain itself is the same as or_run_walker's. */
 int or_run_walker_log(const or_system *sys, uint32_t w, double *xyz, or_walker *acc,
                       uint32_t t0, int32_t n_sweeps, uint32_t measure_start, int32_t m,
                       double *log, int64_t log_cap);

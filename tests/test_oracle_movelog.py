@@ -47,7 +47,7 @@ def test_move_log_follows_stream_decision_and_totals():
     U0, V0 = O.totals(s_, x)
     a = O.walker_init(s_, x)
     log = O.run_walker_log(s_, w, x, a, t0, sweeps, 0xFFFFFFFF, 0)
-    assert log.shape == (n * sweeps, 6)
+    assert log.shape == (n * sweeps, 8)
     for q in range(n * sweeps):
         k, t = q % n, t0 + q // n
         s, xi, _ = O.draw_move(s_, k, t, w)
@@ -110,3 +110,38 @@ def test_fp32_storage_value_rounding_to_L_is_zero():
     assert float(np.float32(x[0, 1])) == L
     r = O.trial_position(s32, x, 1, np.zeros(3))
     assert r[0] == 0.0 and r[1] == 1.0 and r[2] == 1.0
+
+
+def test_aziz_slope_is_the_derivative_of_the_potential():
+    """dV/dr against central differences of the potential itself, across the
+    damping region (x < D), the well and the dispersion tail."""
+    for r in (2.3, 2.7, 2.963, 3.4, 4.0, 4.39, 4.5, 6.0, 9.0, 15.0):
+        h = 1e-5 * r
+        fd = (O.aziz(r + h) - O.aziz(r - h)) / (2 * h)
+        assert abs(O.aziz_deriv(r) - fd) <= 1e-7 * max(1.0, abs(fd)), r
+    # the well's minimum at r_m: the slope changes sign there
+    assert O.aziz_deriv(2.95) < 0.0 < O.aziz_deriv(2.98)
+
+
+def test_move_slopes_sum_the_pair_slopes():
+    """N = 3: the slopes of a move are the sums over the two other atoms of
+    |du/dr| and |dV/dr| at the old and the trial distance, each taken here by
+    central differences of u and V (the pair beyond L/2 adds nothing)."""
+    n = 3
+    s_ = _sys(n)
+    L = s_.L
+    x = np.ascontiguousarray(np.array([[0.3, 2.9, 5.1], [0.2, 0.4, 3.0], [0.1, 0.3, 0.2]]) * (L / 6.0))
+    s, rnew = 0, x[:, 0] + np.array([0.7, -0.2, 0.4])
+    su, sv = O.delta_slopes(s_, x, s, rnew)
+    want_u = want_v = 0.0
+    for i in (1, 2):
+        for p in (rnew, x[:, 0]):
+            d = p - x[:, i]
+            d -= L * np.round(d / L)
+            r = float(np.sqrt(d @ d))
+            h = 1e-6 * r
+            want_u += abs(O.u(s_, r + h) - O.u(s_, r - h)) / (2 * h)
+            if r <= L / 2:
+                want_v += abs(O.aziz(r + h) - O.aziz(r - h)) / (2 * h)
+    assert su == __import__("pytest").approx(want_u, rel=1e-6)
+    assert sv == __import__("pytest").approx(want_v, rel=1e-6)
