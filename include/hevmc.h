@@ -323,6 +323,25 @@ hevmc_status hevmc_eval_config(const hevmc_params *p, const double *xyz, int32_t
                                const double delta[3], double *d_u, double *d_v,
                                double out_el[6]);
 
+/* ---- Entry point that allocates nothing ------------------------------------ */
+
+#define HEVMC_NOALLOC_MAX_N 8192
+
+/* hevmc_eval_config for callers that cannot allocate device memory (code that
+ * runs under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results, bit for bit, as
+ * hevmc_eval_config; the staging buffers (configuration, s, delta, results)
+ * are a fixed device array of the library (196.7 KB per device, held until
+ * the process ends) instead of hipMalloc'ed memory, and the call makes no
+ * hipMalloc, hipFree or other allocating call on the device.  Synchronous, on
+ * the null stream.  Requires p->n <= HEVMC_NOALLOC_MAX_N (HEVMC_EINVAL
+ * otherwise), and the other limits of hevmc_eval_config.  All calls on one
+ * device share that array: calls that overlap on one device (from several
+ * host threads) race. */
+hevmc_status hevmc_eval_config_noalloc(const hevmc_params *p, const double *xyz, int32_t s,
+                                       const double delta[3], double *d_u, double *d_v,
+                                       double out_el[6]);
+
 /* Description of the last error on the calling thread (never NULL). */
 const char *hevmc_last_error(void);
 

@@ -92,8 +92,10 @@ EXPORTS = [
     "hevmc_pair_histogram", "hevmc_sweep_trace", "hevmc_sweep_log", "hevmc_local_energy",
     "hevmc_move_delta", "hevmc_draw_moves", "hevmc_sweep_batch", "hevmc_create", "hevmc_create_on", "hevmc_run",
     "hevmc_sync", "hevmc_get_acc", "hevmc_get_coords", "hevmc_get_sweep", "hevmc_destroy",
-    "hevmc_eval_config", "hevmc_last_error",
+    "hevmc_eval_config", "hevmc_eval_config_noalloc", "hevmc_last_error",
 ]
+
+NOALLOC_MAX_N = 8192   # HEVMC_NOALLOC_MAX_N
 
 _lib = None
 
@@ -132,6 +134,8 @@ def lib():
             "hevmc_get_sweep": [vp, C.POINTER(C.c_uint32)],
             "hevmc_destroy": [vp],
             "hevmc_eval_config": [P, vp, C.c_int32, vp, C.POINTER(C.c_double), C.POINTER(C.c_double), vp],
+            "hevmc_eval_config_noalloc": [P, vp, C.c_int32, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                          vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -325,16 +329,18 @@ def acc_to_numpy(acc):
     return np.ascontiguousarray(a).view(ACC_DTYPE).reshape(a.shape[0])
 
 
-def eval_config(p, xyz, s, delta):
-    """Host-buffer parity entry: returns (dU, dV, [E_L, V, T_PB, T_JF, T_F, U])."""
+def eval_config(p, xyz, s, delta, noalloc=False):
+    """Host-buffer parity entry: returns (dU, dV, [E_L, V, T_PB, T_JF, T_F, U]).
+    noalloc: through hevmc_eval_config_noalloc (no device allocation)."""
     x = np.ascontiguousarray(xyz, dtype=np.float64)
     if x.shape != (3, p.n):
         raise ValueError(f"xyz must have shape (3, {p.n})")
     d = np.ascontiguousarray(delta, dtype=np.float64)
     du, dv = C.c_double(), C.c_double()
     out = np.zeros(6)
-    _check(lib().hevmc_eval_config(C.byref(p), x.ctypes.data_as(C.c_void_p), int(s), d.ctypes.data_as(C.c_void_p),
-                                   C.byref(du), C.byref(dv), out.ctypes.data_as(C.c_void_p)))
+    fn = lib().hevmc_eval_config_noalloc if noalloc else lib().hevmc_eval_config
+    _check(fn(C.byref(p), x.ctypes.data_as(C.c_void_p), int(s), d.ctypes.data_as(C.c_void_p),
+              C.byref(du), C.byref(dv), out.ctypes.data_as(C.c_void_p)))
     return du.value, dv.value, out
 
 

@@ -895,3 +895,125 @@ extern "C" hevmc_status hevmc_eval_config(const hevmc_params *p, const double *x
     (void)hipFree(dout);
     return st;
 }
+
+// ---------------------------------------------------------------------------
+// hevmc_eval_config_noalloc: hevmc_eval_config with its staging buffers in a
+// fixed device array instead of hipMalloc'ed memory.
+//
+// Layout of the array (doubles): [0, 3 NMAX) the configuration (doubles for
+// FP64, floats for FP32 from the same base), then one slot for s (int32), three
+// for delta and eight for the results (dU, dV, then the six local-energy
+// quantities).  Every call overwrites everything it reads back, so nothing has
+// to start at zero.  One copy per device, shared by all calls on that device:
+// calls that overlap on one device race.
+namespace {
+
+constexpr int kNoallocSlotS = 3 * HEVMC_NOALLOC_MAX_N;
+constexpr int kNoallocSlotDelta = kNoallocSlotS + 1;
+constexpr int kNoallocSlotOut = kNoallocSlotDelta + 3;
+constexpr int kNoallocDoubles = kNoallocSlotOut + 8;
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this device's copy of scratch (hipGetSymbolAddress,
+// once per device, with that device current).  Host code uses only this
+// address: the array's own name is a host-side stand-in.
+hevmc_status scratch_on_current_device(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(HEVMC_EDEVICE, "device %d is beyond the %d devices the no-alloc scratch serves", dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return HEVMC_OK;
+}
+
+}  // namespace
+
+extern "C" hevmc_status hevmc_eval_config_noalloc(const hevmc_params *p, const double *xyz, int32_t s,
+                                                  const double delta[3], double *d_u, double *d_v,
+                                                  double out_el[6])
+{
+    if (!p)
+        return fail(HEVMC_EINVAL, "params is NULL");
+    if (p->n > HEVMC_NOALLOC_MAX_N)
+        return fail(HEVMC_EINVAL, "n = %d exceeds the %d atoms the no-alloc scratch holds", p->n,
+                    HEVMC_NOALLOC_MAX_N);
+    hevmc_params q = *p;
+    q.n_walkers = 1;
+    Launch L;
+    hevmc_status st = plan(&q, nullptr, L);
+    if (st != HEVMC_OK)
+        return st;
+    if (!xyz || !delta || !d_u || !d_v || !out_el)
+        return fail(HEVMC_EINVAL, "xyz, delta, d_u, d_v and out_el must not be NULL");
+    if (s < 0 || s >= q.n)
+        return fail(HEVMC_EINVAL, "s = %d is not in [0, %d)", s, q.n);
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(delta[a]))
+            return fail(HEVMC_EINVAL, "delta[%d] is not finite", a);
+    const size_t count = 3 * (size_t)q.n;
+    if ((st = check_host_coords(&q, xyz, count)) != HEVMC_OK)
+        return st;
+    double *sc = nullptr;
+    if ((st = scratch_on_current_device(&sc)) != HEVMC_OK)
+        return st;
+    void *dc = sc;
+    int32_t *ds = reinterpret_cast<int32_t *>(sc + kNoallocSlotS);
+    double *dd = sc + kNoallocSlotDelta, *dout = sc + kNoallocSlotOut;
+    hipError_t he = hipSuccess;
+    if (q.precision == HEVMC_FP32) {
+        // rounded to float on the host through a fixed stack buffer, chunk by chunk
+        float tmp[1024];
+        const float Lf = (float)box_side(&q);
+        float *dst = static_cast<float *>(dc);
+        for (size_t i0 = 0; i0 < count && he == hipSuccess; i0 += 1024) {
+            const size_t m = std::min<size_t>(1024, count - i0);
+            for (size_t i = 0; i < m; ++i) {
+                const float v = (float)xyz[i0 + i];
+                tmp[i] = v < Lf ? v : 0.0f;   // a value just below L may round up to L
+            }
+            he = hipMemcpy(dst + i0, tmp, m * sizeof(float), hipMemcpyHostToDevice);
+        }
+    } else {
+        he = hipMemcpy(dc, xyz, count * sizeof(double), hipMemcpyHostToDevice);
+    }
+    if (he == hipSuccess)
+        he = hipMemcpy(ds, &s, sizeof(int32_t), hipMemcpyHostToDevice);
+    if (he == hipSuccess)
+        he = hipMemcpy(dd, delta, 3 * sizeof(double), hipMemcpyHostToDevice);
+    if (he != hipSuccess)
+        return hip_fail(he, "argument upload");
+    if ((st = launched(launch_move_delta(L, dc, ds, dd, dout), "move-delta kernel launch")) != HEVMC_OK)
+        return st;
+    if ((st = launched(launch_local_energy(L, dc, dout + 2), "local-energy kernel launch")) != HEVMC_OK)
+        return st;
+    double host[8];
+    he = hipMemcpy(host, dout, 8 * sizeof(double), hipMemcpyDeviceToHost);
+    if (he != hipSuccess)
+        return hip_fail(he, "result download");
+    *d_u = host[0];
+    *d_v = host[1];
+    for (int i = 0; i < 6; ++i)
+        out_el[i] = host[2 + i];
+    return HEVMC_OK;
+}
