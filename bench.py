@@ -9,8 +9,10 @@ Warm-up steps (the same launches) double as equilibration; accumulators restart
 with the first timed step.
 
 Prints one JSON line: moves/s, the roofline of the sweep kernel (vector ALU,
-FP64) from per-launch HIP events, and the CPU oracle timed on the host cores on
-a bounded sample of the same workload.
+FP64) from per-launch HIP events, the CPU oracle timed on the host cores on
+a bounded sample of the same workload, and a bounded serving block (the
+served p50/p99 time-to-1 mK/atom half of the metric, with censoring flagged
+and the offered rate against the GPU's capacity for the request mix).
 """
 import argparse
 import json
@@ -59,6 +61,10 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-time-limit", type=float, default=None,
                     help="stop serving after this many seconds; unfinished requests are reported as censored")
+    ap.add_argument("--serve-block-requests", type=int, default=40,
+                    help="requests of the stream served in the throughput line's bounded serving block")
+    ap.add_argument("--serve-block-seconds", type=float, default=90.0,
+                    help="wall-time limit of the bounded serving block (0: no serving block)")
     ap.add_argument("--precision-check", action="store_true",
                     help="instead of the throughput line, the FP32 form against FP64 at N=2048 with 1024 walkers "
                          "on identical seeds: chain energies and per-configuration local-energy error in mK/atom")
@@ -67,6 +73,9 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the workload, run 5 plain device copies of MIB MiB (the reference "
                          "kernel for scaling HBM byte counters) and exit")
+    ap.add_argument("--replica-decorrelation", action="store_true",
+                    help="instead of the throughput line, how fast replicas of equilibrated walkers decorrelate "
+                         "(equilibrate-then-replicate), against independently equilibrated walkers")
     ap.add_argument("--b-scan", action="store_true",
                     help="instead of the throughput line, one run of the workload with per-sample records and "
                          "the correlated-sampling curve E(b') around its b, with one direct run to check it")
@@ -139,6 +148,152 @@ def serve(args):
                           "arrival_s": round(r.arrival, 4), "admitted_s": r.admitted, "done_s": r.done,
                           "sweeps": r.sweeps, "E_per_atom_K": r.energy, "se_K": r.se} for r in reqs],
         },
+    }
+    print(json.dumps(line), flush=True)
+
+
+def serve_block(args):
+    """The serving half of the metric, bounded in time: the first
+    args.serve_block_requests requests of the seeded Poisson stream (20/s)
+    arrive in real time and are served until each reaches SE <= 1 mK/atom or
+    the wall-time limit passes.  Requests still running then are censored
+    (their elapsed time is a lower bound, and so are the percentiles).  The
+    offered rate is set against the capacity the GPU sustains for this
+    request mix, estimated from the work each request needs (its sweeps to
+    the target, extrapolated from its last stop-rule check when unfinished)."""
+    import numpy as np
+
+    from paper_1312_1282_amd import configs, serving
+
+    reqs = serving.request_stream(args.serve_block_requests, rate=args.serve_rate)
+    server = serving.Server()
+    t0 = time.perf_counter()
+    server.run(reqs, realtime=True, time_limit=args.serve_block_seconds)
+    wall = time.perf_counter() - t0
+    lat = serving.latency_summary(reqs, server.censored_at)
+    cap, n_pred = serving.capacity_estimate(server, reqs, wall)
+    done = [r for r in reqs if r.done is not None]
+    return {
+        "workload": "he4_serving_stream",
+        "requests": len(reqs),
+        "offered_rate_per_s": args.serve_rate,
+        "wall_limit_s": args.serve_block_seconds,
+        "wall_s": wall,
+        **lat,
+        "completed_per_s": len(done) / wall if wall > 0 else 0.0,
+        "capacity_per_s": cap,
+        "capacity_basis": f"pair terms per second while serving / mean predicted pair terms per request "
+                          f"({n_pred} of {len(reqs)} requests had a prediction)",
+        "highest_sustainable_rate_per_s": cap,
+        "offered_over_capacity": (args.serve_rate / cap) if cap else None,
+        "moves_per_s": server.moves / wall if wall > 0 else 0.0,
+        "pair_terms_per_s": server.pair_terms / wall if wall > 0 else 0.0,
+        "launches": server.launches,
+        "target_se_K": server.target_se,
+        "rejected": sum(1 for r in reqs if r.rejected),
+        "requests_detail": [{"rid": r.rid, "n": r.n, "walkers": r.walkers, "precision": r.precision,
+                             "arrival_s": round(r.arrival, 3),
+                             "done_s": None if r.done is None else round(r.done, 3), "sweeps": r.sweeps,
+                             "se_mK": None if r.se is None else round(r.se * 1e3, 3),
+                             "predicted_sweeps": (None if serving.predicted_sweeps(server, r) is None
+                                                  else int(serving.predicted_sweeps(server, r)))}
+                            for r in reqs],
+    }
+
+
+def _corr_by_lag(a, b):
+    """Correlation coefficient over pairs of a[:, t] and b[:, t], for each t."""
+    import numpy as np
+
+    a = a - a.mean(axis=0)
+    b = b - b.mean(axis=0)
+    return (a * b).sum(axis=0) / np.sqrt((a * a).sum(axis=0) * (b * b).sum(axis=0))
+
+
+def _iat(x, cut=6.0):
+    """Integrated autocorrelation time (in samples) of series x[w, t], averaged
+    over w, summing the autocorrelation until the window reaches cut times it
+    (Sokal's automatic window)."""
+    import numpy as np
+
+    x = x - x.mean(axis=1, keepdims=True)
+    var = (x * x).mean()
+    tau = 0.5
+    for k in range(1, x.shape[1] // 2):
+        tau += (x[:, :-k] * x[:, k:]).mean() / var
+        if k >= cut * tau:
+            break
+    return float(tau)
+
+
+def replica_decorrelation(args, n=256, seeds=64, copies=8, equil=400, sweeps=300):
+    """Equilibrate-then-replicate (Sec. 4.4): `seeds` walkers equilibrate
+    for `equil` sweeps; each is copied to `copies` walkers, which restart
+    their running totals from the copy and move on with their own random
+    numbers, a local-energy sample every sweep.  rho(t) is the correlation of
+    E_L between two copies of the same seed t sweeps after the copy (1 at
+    t = 0), against the same statistic for walkers equilibrated
+    independently (pairs of different seeds), and beside the integrated
+    autocorrelation time of E_L along one chain."""
+    import numpy as np
+    import torch
+
+    from paper_1312_1282_amd import abi, configs
+
+    torch.cuda.set_device(0)
+    wl = configs.C1_SMALL_FP64.with_(name="he4_replicas", n=n, walkers=seeds * copies, m=1)
+    W = wl.walkers
+    p_seed = abi.params_for(wl, n_walkers=seeds)
+    p_all = abi.params_for(wl)
+    coords, acc = abi.alloc_state(p_all)
+    rows = abi.alloc_rows(p_all)
+    abi.init_walkers(p_seed, coords[:seeds], acc[:seeds], fcc_start=True, rows=rows[:seeds])
+    abi.sweep(p_seed, coords[:seeds], acc[:seeds], 0, equil, abi.NO_MEASURE, 0, rows=rows[:seeds])
+    # walker j (j >= seeds) takes seed j mod seeds; its Philox walker id is j
+    src = torch.arange(seeds, W, device="cuda") % seeds
+    coords[seeds:] = coords[src]
+    rows[seeds:] = rows[src]
+    abi.init_walkers(p_all, coords, acc, fcc_start=False, rows=rows)
+    tr = torch.zeros((W, sweeps, 6), dtype=torch.float64, device="cuda")
+    abi.sweep(p_all, coords, acc, equil, sweeps, equil, 1, rows=rows, trace=tr)
+    torch.cuda.synchronize()
+    e = tr[:, :, 0].cpu().numpy() / n            # E_L per atom, [walker, sample]
+    fam = np.arange(W) % seeds                    # seed of each walker
+    # pairs of copies of one seed: (seed + a*seeds, seed + b*seeds), a < b
+    pa, pb = [], []
+    for a in range(copies):
+        for b in range(a + 1, copies):
+            pa.append(np.arange(seeds) + a * seeds)
+            pb.append(np.arange(seeds) + b * seeds)
+    pa, pb = np.concatenate(pa), np.concatenate(pb)
+    assert np.all(fam[pa] == fam[pb])
+    rho = _corr_by_lag(e[pa], e[pb])
+    # independent pairs: copies of different seeds
+    qa = np.arange(seeds)
+    qb = (np.arange(seeds) + 1) % seeds + seeds
+    rho_ind = _corr_by_lag(e[qa], e[qb])
+    below = np.nonzero(rho < np.exp(-1.0))[0]
+    t_e = int(below[0]) + 1 if len(below) else None
+    noise = float(np.std(rho_ind))
+    below2 = np.nonzero(rho < 2.0 * noise)[0]
+    t_noise = int(below2[0]) + 1 if len(below2) else None
+    # integrated autocorrelation time of E_L along the chains (second half)
+    iat = _iat(e[:, sweeps // 2:])
+    line = {
+        "metric": "replica decorrelation (equilibrate-then-replicate)",
+        "value": t_e,
+        "unit": "sweeps after the copy until the E_L correlation of two copies falls below 1/e",
+        "n_gpus": 1,
+        "dtype": "f64",
+        "data": "synthetic: fcc-started liquid 4He walkers",
+        "config": {"workload": wl.name, "n_atoms": n, "seeds": seeds, "copies": copies, "equil_sweeps": equil,
+                   "traced_sweeps": sweeps, "density_per_A3": wl.density, "b_A": wl.b},
+        "rho_by_sweep": [round(float(x), 4) for x in rho[:60]],
+        "rho_independent_rms": noise,
+        "sweeps_to_noise_level": t_noise,
+        "el_integrated_autocorrelation_sweeps": iat,
+        "samples_independent_pairs": int(len(qa)),
+        "samples_copy_pairs": int(len(pa)),
     }
     print(json.dumps(line), flush=True)
 
@@ -335,6 +490,9 @@ def main():
     if args.b_scan:
         b_scan(args)
         return
+    if args.replica_decorrelation:
+        replica_decorrelation(args)
+        return
     if args.precision_check:
         precision_check(args)
         return
@@ -444,6 +602,8 @@ def main():
         cb["gpu_over_cpu"] = value / cb["value"]
         cb["gpu_over_single_core"] = value / cb["single_core_moves_per_s"]
         line["cpu_baseline"] = cb
+    if args.serve_block_seconds > 0 and args.serve_block_requests > 0:
+        line["serving"] = serve_block(args)
     print(json.dumps(line), flush=True)
 
 

@@ -53,6 +53,8 @@ class Request:
     result: np.ndarray = None
     slot0: int = None
     replicated: bool = False
+    # another class had a launch in flight when this request was admitted
+    admitted_during_flight: bool = False
     rejected: str = None
     failed: str = None      # set when a walker's state turns non-finite
 
@@ -159,6 +161,7 @@ class Server:
         self.used_budget = 0.0
         self.launches = 0
         self.moves = 0
+        self.pair_terms = 0
         self.log = None
         self.censored_at = None
 
@@ -203,6 +206,7 @@ class Server:
             return False
         req.slot0 = a
         req.admitted = now
+        req.admitted_during_flight = any(q.event is not None for q in self.pools.values() if q is not pool)
         req.sweeps = 0
         self.used_budget += lds_total
         p = self.params(req)
@@ -299,6 +303,7 @@ class Server:
         pool.in_flight = reqs
         self.launches += 1
         self.moves += sum(self.seeds(r) * r.n for r in reqs) * self.quantum_for(pool.n)
+        self.pair_terms += sum(self.seeds(r) * r.n * (r.n - 1) for r in reqs) * self.quantum_for(pool.n)
 
     def _finish_quantum(self, pool, now):
         """The launch of pool is complete: advance counters, run stop checks."""
@@ -383,6 +388,37 @@ class Server:
                 time.sleep(0.0005)
         torch.cuda.synchronize()
         return requests
+
+
+def predicted_sweeps(server, req):
+    """Sweeps a request needs to reach the target: its own count if it is
+    done; else, from its last stop-rule check, the measured sweeps scaled by
+    (SE / target)^2 (the SE of a mean over samples falls as one over the
+    square root of their number); None before its first check."""
+    if req.done is not None:
+        return req.sweeps
+    if req.se is None or not np.isfinite(req.se):
+        return None
+    ms = server.measure_start()
+    measured = req.sweeps - ms
+    if measured <= 0:
+        return None
+    return ms + measured * max(1.0, (req.se / server.target_se) ** 2)
+
+
+def capacity_estimate(server, requests, busy_s):
+    """Requests per second the GPU sustains for this request mix: pair terms
+    per second while serving over the mean pair terms a request needs (from
+    predicted_sweeps, over the requests that have a prediction)."""
+    work = []
+    for r in requests:
+        sw = predicted_sweeps(server, r)
+        if sw is not None:
+            work.append(r.walkers * r.n * (r.n - 1) * sw)
+    if not work or busy_s <= 0 or server.pair_terms == 0:
+        return None, len(work)
+    rate = server.pair_terms / busy_s
+    return rate / float(np.mean(work)), len(work)
 
 
 def latency_summary(requests, censored_at=None):

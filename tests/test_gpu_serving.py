@@ -3,6 +3,7 @@ request's result is the same alone and in a mix, bit for bit."""
 import numpy as np
 import pytest
 
+import oracle as O
 from paper_1312_1282_amd import abi, configs, serving
 
 torch = pytest.importorskip("torch")
@@ -115,3 +116,70 @@ def test_replicated_server_alone_and_in_mix_and_energy():
     assert not plain.replicated
     assert abs(alone.energy - plain.energy) < 4.0 * np.hypot(alone.se, plain.se), (alone.energy, plain.energy)
 
+
+
+def test_freed_slots_and_admission_during_flight_keep_results():
+    """Continuous batching proper: one request per class at a time and a pool
+    of 64 slots per class, so later requests of a class wait for an earlier one
+    to retire and take its freed slots, and are admitted while the other class
+    has a launch in flight; staggered real-time arrivals.  Every result equals
+    the same request served alone, bit for bit."""
+    mk = lambda: [_req(0, 108, 64, abi.FP64, 0.0200, 2.8, 41), _req(1, 256, 64, abi.FP32, 0.0215, 3.0, 42),
+                  _req(2, 108, 64, abi.FP64, 0.0230, 3.1, 43), _req(3, 256, 48, abi.FP32, 0.0205, 2.9, 44),
+                  _req(4, 108, 32, abi.FP64, 0.0219, 2.94, 45)]
+    kw = dict(target_se=4e-3, equil=20, check_every=10, min_samples=2, quantum=5, max_requests_per_class=1,
+              slots_per_class=64)
+    reqs = mk()
+    for k, r in enumerate(reqs):
+        r.arrival = 0.02 * k
+    mix = serving.Server(**kw).run(reqs, realtime=True)
+    for r in mix:
+        assert r.done is not None and r.rejected is None and r.failed is None, r.rid
+    # later requests of a class reuse the slots of the one before them
+    assert mix[2].slot0 == mix[0].slot0 and mix[2].admitted >= mix[0].done
+    assert mix[4].slot0 == mix[2].slot0 and mix[4].admitted >= mix[2].done
+    assert mix[3].slot0 == mix[1].slot0 and mix[3].admitted >= mix[1].done
+    assert any(r.admitted_during_flight for r in mix[1:])
+    for k in range(5):
+        alone = serving.Server(**{**kw, "max_requests_per_class": 16, "slots_per_class": 8192}).run(
+            [mk()[k]], realtime=False)[0]
+        assert alone.sweeps == mix[k].sweeps, k
+        assert alone.result.tobytes() == mix[k].result.tobytes(), (k, _acc_diff(alone.result, mix[k].result))
+
+
+def test_replicated_request_follows_the_oracle():
+    """Equilibrate-then-replicate through the oracle, in lockstep: the
+    request's K seed walkers equilibrate alone (oracle: walker ids 0..K-1 from
+    their fcc starts), every walker j then takes a copy of seed j mod K, its
+    running totals and accumulators restart from that configuration, and it
+    moves on with its own random numbers (walker id j) through the
+    decorrelation and measured sweeps.  The server's final accumulators and
+    configurations equal the oracle's replay of the same steps."""
+    K, W, n = 4, 16, 108
+    req = _req(0, n, W, abi.FP64, 0.0219, 2.94, 51)
+    kw = dict(target_se=1.0, equil=20, check_every=10, min_samples=2, quantum=5, replicate=K, decorrelate=10)
+    server = serving.Server(**kw)
+    r = server.run([req], realtime=False)[0]
+    assert r.done is not None and r.replicated
+    pool = server.pools[(n, abi.FP64)]
+    xg = pool.coords[r.slot0:r.slot0 + W].cpu().numpy()
+    ag = r.result
+    p = r.params()
+    s_ = O.system(n, O.box_side(n, req.density), req.b, hbar2_over_m=configs.HBAR2_OVER_M,
+                  step_sigma=p.step_sigma, seed=req.seed)
+    seeds = []
+    for w in range(K):
+        x = O.fcc_start(s_, w)
+        a = O.walker_init(s_, x)
+        O.run_walker(s_, w, x, a, 0, server.equil, 0xFFFFFFFF, 0)
+        seeds.append(x)
+    ms = server.measure_start()
+    for j in range(W):
+        x = np.ascontiguousarray(seeds[j % K].copy())
+        a = O.walker_init(s_, x)
+        O.run_walker(s_, j, x, a, server.equil, r.sweeps - server.equil, ms, server.m)
+        assert ag["n_acc"][j] == a.n_acc and ag["n_try"][j] == a.n_try, j
+        assert ag["n_samples"][j] == a.n_samples == (r.sweeps - ms) // server.m, j
+        assert np.max(np.abs(xg[j] - x)) < 1e-9, j
+        assert ag["sum_e"][j] + ag["c_e"][j] == pytest.approx(a.sum_e + a.c_e, rel=1e-10), j
+        assert ag["u_run"][j] == pytest.approx(a.u_run, rel=1e-10, abs=1e-9), j
