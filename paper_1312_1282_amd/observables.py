@@ -58,3 +58,62 @@ def reweight_b(records, b, b_primes, n_atoms):
                     "ess": float(w.sum() ** 2 / (w * w).sum())})
     return out
 
+
+
+def autocorrelation(x, kmax=None):
+    """R(k) of a stationary sequence and its autocorrelation time m_c (the
+    definitions of Sec. 4.1): R(k) = sum_i (A_i - <A>)(A_{i+k} - <A>) /
+    sum_i (A_i - <A>)^2, and m_c = sum_{k >= 1} R(k), the sum cut where R first
+    falls to zero or below (beyond that the estimate is noise).  Returns
+    (R[0..kmax], m_c)."""
+    a = np.asarray(x, dtype=np.float64)
+    a = a - a.mean()
+    n = len(a)
+    kmax = n // 4 if kmax is None else min(kmax, n - 1)
+    den = (a * a).sum()
+    R = np.array([(a[: n - k] * a[k:]).sum() / den for k in range(kmax + 1)])
+    mc = 0.0
+    for k in range(1, kmax + 1):
+        if R[k] <= 0.0:
+            break
+        mc += R[k]
+    return R, mc
+
+
+def blocking(x):
+    """Flyvbjerg-Petersen reblocking of a correlated sequence (the reblocking
+    the paper names as an alternative to summing R(k), Sec. 4.1): at level l
+    the sequence is averaged in consecutive pairs l times, and the standard
+    error of the mean is estimated as if the blocks were independent,
+    se_l = sqrt(var_l / (n_l - 1)), with its own uncertainty
+    se_l / sqrt(2 (n_l - 1)).  Levels run while n_l >= 4.  Returns a list of
+    (n_l, se_l, dse_l)."""
+    a = np.asarray(x, dtype=np.float64).copy()
+    out = []
+    while len(a) >= 4:
+        n = len(a)
+        var = a.var()                      # population variance of the blocks
+        se = np.sqrt(var / (n - 1))
+        out.append((n, float(se), float(se / np.sqrt(2.0 * (n - 1)))))
+        if n % 2:
+            a = a[:-1]
+        a = 0.5 * (a[0::2] + a[1::2])
+    return out
+
+
+def blocking_se(x):
+    """Standard error of the mean of a correlated sequence from reblocking:
+    the estimate at the first level after which reblocking stops raising it,
+    i.e. the next two levels exceed it by no more than its own uncertainty
+    (once and twice over); if no level qualifies, the largest estimate.
+    Returns (se, level)."""
+    lv = blocking(x)
+    if not lv:
+        return float("nan"), -1
+    for l in range(len(lv)):
+        se, dse = lv[l][1], lv[l][2]
+        nxt = [lv[m][1] for m in (l + 1, l + 2) if m < len(lv)]
+        if len(nxt) >= 1 and nxt[0] - se <= dse and (len(nxt) < 2 or nxt[1] - se <= 2.0 * dse):
+            return se, l
+    k = int(np.argmax([se for _, se, _ in lv]))
+    return lv[k][1], k
