@@ -184,11 +184,11 @@ __device__ __forceinline__ double rsq_nr(double x)
 // arguments).  Cody-Waite reduction a = k ln2 + f, |f| <= ln2/2, with the
 // two-part ln2 of fdlibm (its high part has trailing zero bits, so k*ln2_hi is
 // exact), e^f by its Taylor series to degree 12 (truncation < 2e-16 relative),
-// scaled by 2^k.  Arguments below -708 are clamped there (the result, ~3e-308,
-// is zero for every sum it enters).
+// scaled by 2^k.  For a below about -745 the scaling underflows to zero, the
+// value of e^a in FP64 (a = -inf, the distance-zero pair of an atom with
+// itself, gives NaN, which the callers' masks discard).
 __device__ __forceinline__ double exp_neg(double a)
 {
-    a = fmax(a, -708.0);
     const double k = rint(a * 1.4426950408889634);
     double f = fma(-k, 6.93147180369123816490e-01, a);
     f = fma(-k, 1.90821492927058770002e-10, f);
@@ -208,9 +208,18 @@ __device__ __forceinline__ double exp_neg(double a)
     return ldexp(q, (int)k);
 }
 
+// v if keep, else v with its high word cleared: a number below 2^-1022 in
+// magnitude, which no sum it enters can feel (one 32-bit select instead of
+// two; a masked NaN also becomes such a number).
+__device__ __forceinline__ double keep_or_tiny(bool keep, double v)
+{
+    return __hiloint2double(keep ? __double2hiint(v) : 0, __double2loint(v));
+}
+
 // --------------------------------------------------------------------------
 // Pair terms at squared min-image distance r2 (Eqs. (8), (9); HFD-B(HE)).
-// u and V are zero beyond the inclusive cutoff L/2; callers mask i == s
+// u and V are zero beyond the inclusive cutoff L/2 (in the FP64 terms of the
+// row-sum sweep, keep_or_tiny's numerical zero); callers mask i == s
 // (r2 = 0 gives non-finite terms that the mask discards).
 
 // FP64: u(r) and V(r).
@@ -255,18 +264,18 @@ __device__ __forceinline__ double pair_u_ri(const KParams &p, double r2, double 
     const double rpi = rcp_nr(p.L - r);
     const double ri2 = ri * ri, rpi2 = rpi * rpi;
     const double uu = fma(p.c5, fma(ri2 * ri2, ri, rpi2 * rpi2 * rpi), p.u0);
-    return r2 <= p.h2 ? uu : 0.0;
+    return keep_or_tiny(r2 <= p.h2, uu);
 }
 
 // u(r) for a pair that counts if `keep` (the moved atom itself does not):
-// zero beyond the cutoff or when !keep, with one select for both.
+// (numerically) zero beyond the cutoff or when !keep, with one select for both.
 __device__ __forceinline__ double pair_u_in(const KParams &p, double r2, double ri, bool keep)
 {
     const double r = r2 * ri;
     const double rpi = rcp_nr(p.L - r);
     const double ri2 = ri * ri, rpi2 = rpi * rpi;
     const double uu = fma(p.c5, fma(ri2 * ri2, ri, rpi2 * rpi2 * rpi), p.u0);
-    return (keep && r2 <= p.h2) ? uu : 0.0;
+    return keep_or_tiny(keep && r2 <= p.h2, uu);
 }
 
 // FP64: V(r) alone, given r^2 and 1/r.
@@ -286,7 +295,7 @@ __device__ __forceinline__ double pair_v_ri(const KParams &p, double r2, double 
         F = exp_neg(-(q * q));
     }
     const double vv = az::eps * fma(-F, disp, rep);
-    return r2 <= p.h2 ? vv : 0.0;
+    return keep_or_tiny(r2 <= p.h2, vv);
 }
 
 // FP32 form: same terms in single precision with the hardware reciprocal,
@@ -470,12 +479,19 @@ __device__ __forceinline__ bool metropolis_accept_log(double du, double log_xi)
 // scalars and added in a fixed order.  The total depends only on the data and
 // the lane layout, and every lane holds the same value.  All 64 lanes must be
 // active.
+// Every lane has a valid source under the four controls used here, so the
+// moves need no prior value in their destination (no zeroing moves).
 template <int CTRL>
 __device__ __forceinline__ double dpp_double(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ float lane_value(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
 __device__ __forceinline__ double lane_value(double v, int lane)

@@ -611,6 +611,18 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
             const int blab = bs;           // the atom's label (bs becomes its slot)
             if (sorted)
                 bs = slot_of[bs];
+            // Old and trial position of micro-step k0 + lane, taken here from
+            // the positions in LDS, off the moves' critical path.  A lane's
+            // pair goes stale when its atom is moved by an accepted earlier
+            // micro-update of the batch (bit `lane` of `stale`), or is the
+            // atom accepted just before the batch, whose new LDS copy other
+            // waves may not see yet; a stale micro-step forms both positions
+            // again when it runs, from the forwarded copy or from LDS.
+            const T box = sx[bs], boy = sy[bs], boz = sz[bs];
+            const T bnx = trial_coord<T>((double)box + bdx, p);
+            const T bny = trial_coord<T>((double)boy + bdy, p);
+            const T bnz = trial_coord<T>((double)boz + bdz, p);
+            uint64_t stale = last_s >= 0 ? __builtin_amdgcn_ballot_w64(bs == last_s) : 0ull;
             const int kend = min(64, n - k0);
             for (int j = 0; j < kend; ++j) {
                 const int k = k0 + j;
@@ -619,16 +631,26 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                 const int64_t q_log = (int64_t)it * n + k;   // this micro-update's record
                 const int s = readlane_i(bs, j);
                 const double lxi = lane_value(blx, j);
-                const double dx = lane_value(bdx, j), dy = lane_value(bdy, j), dz = lane_value(bdz, j);
-                T ox, oy, oz;
-                if (s == last_s) {
-                    ox = lx; oy = ly; oz = lz;
+                T ox, oy, oz, nx, ny, nz;
+                if ((stale >> j) & 1ull) {
+                    if (s == last_s) {
+                        ox = lx; oy = ly; oz = lz;
+                    } else {
+                        ox = sx[s]; oy = sy[s]; oz = sz[s];
+                    }
+                    nx = trial_coord<T>((double)ox + lane_value(bdx, j), p);
+                    ny = trial_coord<T>((double)oy + lane_value(bdy, j), p);
+                    nz = trial_coord<T>((double)oz + lane_value(bdz, j), p);
                 } else {
-                    ox = sx[s]; oy = sy[s]; oz = sz[s];
+                    ox = lane_value(box, j); oy = lane_value(boy, j); oz = lane_value(boz, j);
+                    nx = lane_value(bnx, j); ny = lane_value(bny, j); nz = lane_value(bnz, j);
                 }
-                const T nx = trial_coord<T>((double)ox + dx, p);
-                const T ny = trial_coord<T>((double)oy + dy, p);
-                const T nz = trial_coord<T>((double)oz + dz, p);
+                // the later micro-steps of the batch that move atom s (called
+                // after an accepted micro-update of atom s)
+                auto mark_stale = [&]() {
+                    const uint64_t later = j >= 63 ? 0ull : (~0ull << (j + 1));
+                    stale |= __builtin_amdgcn_ballot_w64(bs == s) & later;
+                };
                 const bool owner = (tid == s % NT);
                 // the record of this micro-update (label, decision, dU; dV when known)
                 auto log_move = [&](bool acc_, double du_, double dv_) {
@@ -716,6 +738,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                             reg_set<0, kRegChunks>(rr, js, SU);
                         }
                         last_s = s;
+                        mark_stale();
                         lx = nx; ly = ny; lz = nz;
                     } else {
                         last_s = -1;
@@ -828,14 +851,14 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                                     const T vo = pair_v_ri(p, r2o, rio);
                                     const T vn = pair_v_ri(p, r2n_[jj], rin_[jj]);
                                     const bool other = live && (i != s);
-                                    const double dr = other ? (double)un_[jj] - (double)uo : 0.0;
+                                    const double dr = keep_or_tiny(other, (double)un_[jj] - (double)uo);
                                     if constexpr (kReg && kCacheRow) {
                                         cr[jj] += dr;
                                         ru[i] = cr[jj];
                                     } else if (live) {
                                         ru[i] += dr;
                                     }
-                                    dvl += other ? (double)vn - (double)vo : 0.0;
+                                    dvl += keep_or_tiny(other, (double)vn - (double)vo);
                                 }
                             }
                         };
@@ -869,6 +892,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                             }
                         }
                         last_s = s;
+                        mark_stale();
                         lx = nx; ly = ny; lz = nz;
                     } else {
                         last_s = -1;
@@ -907,6 +931,7 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                             sx[s] = nx; sy[s] = ny; sz[s] = nz;
                         }
                         last_s = s;
+                        mark_stale();
                         lx = nx; ly = ny; lz = nz;
                     } else {
                         last_s = -1;
