@@ -73,6 +73,12 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the workload, run 5 plain device copies of MIB MiB (the reference "
                          "kernel for scaling HBM byte counters) and exit")
+    ap.add_argument("--c1", action="store_true",
+                    help="instead of the throughput line, the single-walker run (N=108, 200 + 1000 sweeps, a local "
+                         "energy every sweep) with its error from reblocking and from the autocorrelation time")
+    ap.add_argument("--tsigma", action="store_true",
+                    help="instead of the throughput line, t sigma^2 (time x squared standard error of E/N, "
+                         "s mK^2; Sec. 7.3) of the GPU at N=512 and N=2048 and of the oracle at N=108 and N=2048")
     ap.add_argument("--replica-decorrelation", action="store_true",
                     help="instead of the throughput line, how fast replicas of equilibrated walkers decorrelate "
                          "(equilibrate-then-replicate), against independently equilibrated walkers")
@@ -199,6 +205,135 @@ def serve_block(args):
                                                   else int(serving.predicted_sweeps(server, r)))}
                             for r in reqs],
     }
+
+
+def c1_run(args, equil=200, measured=1000):
+    """The single-walker workload (N=108, seed 1, walker id 0): E/N with the
+    standard error of one correlated chain, by Flyvbjerg-Petersen reblocking
+    of its E_L samples and by Eq. (10) with the autocorrelation time m_c
+    summed from R(k) (Sec. 4.1)."""
+    import numpy as np
+    import torch
+
+    from paper_1312_1282_amd import abi, configs, observables
+
+    torch.cuda.set_device(0)
+    wl = configs.C1_SMALL_FP64
+    p = abi.params_for(wl)
+    coords, acc = abi.alloc_state(p)
+    rows = abi.alloc_rows(p)
+    abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
+    abi.sweep(p, coords, acc, 0, equil, abi.NO_MEASURE, 0, rows=rows)
+    tr = torch.zeros((1, measured // wl.m, 6), dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    abi.sweep(p, coords, acc, equil, measured, equil, wl.m, rows=rows, trace=tr)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    e = tr[0, :, 0].cpu().numpy() / wl.n
+    a = abi.acc_to_numpy(acc)
+    se_blk, level = observables.blocking_se(e)
+    R, mc = observables.autocorrelation(e, kmax=100)
+    se_eq10 = float(e.std() / np.sqrt(len(e)) * np.sqrt(1.0 + 2.0 * mc))
+    line = {
+        "metric": "single-walker E/N with its correlated-chain error",
+        "value": float(e.mean()),
+        "unit": "K per atom",
+        "n_gpus": 1,
+        "dtype": "f64",
+        "data": "synthetic: fcc-started liquid 4He walker",
+        "config": {"workload": wl.name, "n_atoms": wl.n, "walkers": 1, "equil_sweeps": equil,
+                   "measured_sweeps": measured, "energy_every": wl.m, "seed": wl.seed},
+        "se_blocking_K": se_blk,
+        "blocking_level": level,
+        "blocking_levels": [[n_, se_, dse_] for n_, se_, dse_ in observables.blocking(e)],
+        "se_naive_K": float(e.std() / np.sqrt(len(e))),
+        "autocorrelation_time_samples": mc,
+        "se_eq10_K": se_eq10,
+        "acceptance": float(a["n_acc"][0] / a["n_try"][0]),
+        "seconds": dt,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def gpu_tsigma(n, walkers, equil, measured, m=5):
+    """t sigma^2 of the GPU path: W walkers from the fcc start equilibrate
+    for `equil` sweeps, then `measured` sweeps with a local energy every m
+    sweeps; t is the GPU time of the measured sweeps (HIP events) and sigma
+    the standard error of E/N over the walkers' means (independent chains,
+    Eq. (10) with several chains)."""
+    import numpy as np
+    import torch
+
+    from paper_1312_1282_amd import abi, configs
+
+    wl = configs.C2_N2048_FP64.with_(name=f"he4_n{n}_w{walkers}_fp64", n=n, walkers=walkers, m=m)
+    p = abi.params_for(wl)
+    coords, acc = abi.alloc_state(p)
+    rows = abi.alloc_rows(p)
+    abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
+    abi.sweep(p, coords, acc, 0, equil, abi.NO_MEASURE, 0, rows=rows)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in range(0, measured, 50):
+        abi.sweep(p, coords, acc, equil + k, min(50, measured - k), equil, m, stream=stream, rows=rows)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3
+    a = abi.acc_to_numpy(acc)
+    ew = (a["sum_e"] + a["c_e"]) / a["n_samples"] / n
+    se = float(ew.std(ddof=1) / np.sqrt(len(ew)))
+    return {"n": n, "walkers": walkers, "equil_sweeps": equil, "measured_sweeps": measured, "energy_every": m,
+            "E_per_atom_K": float(ew.mean()), "se_mK": se * 1e3, "seconds": t, "tsigma2_s_mK2": t * (se * 1e3) ** 2}
+
+
+def cpu_baseline_tsigma(n, walkers, equil, measured, m=5):
+    """The oracle's t sigma^2 on the host cores (the CPU baseline of the
+    same figure): one walker per thread from the fcc start, `equil` sweeps,
+    then `measured` sweeps with a local energy every m; t is the wall time of
+    the measured sweeps, sigma the standard error of E/N over the walkers."""
+    import numpy as np
+
+    import oracle as O
+    from paper_1312_1282_amd import configs
+
+    s_ = O.system(n, O.box_side(n, configs.RHO_EQ), configs.C2_N2048_FP64.b, hbar2_over_m=configs.HBAR2_OVER_M,
+                  step_sigma=configs.C2_N2048_FP64.step_sigma, seed=1)
+    xyz = np.stack([O.fcc_start(s_, w) for w in range(walkers)])
+    accs = (O.Walker * walkers)(*[O.walker_init(s_, xyz[w]) for w in range(walkers)])
+    O.run_walkers(s_, 0, xyz, accs, 0, equil, 0xFFFFFFFF, 0, walkers)
+    t0 = time.perf_counter()
+    O.run_walkers(s_, 0, xyz, accs, equil, measured, equil, m, walkers)
+    t = time.perf_counter() - t0
+    ew = np.array([(a.sum_e + a.c_e) / a.n_samples / n for a in accs])
+    se = float(ew.std(ddof=1) / np.sqrt(len(ew)))
+    return {"n": n, "walkers": walkers, "threads": walkers, "equil_sweeps": equil, "measured_sweeps": measured,
+            "energy_every": m, "E_per_atom_K": float(ew.mean()), "se_mK": se * 1e3, "seconds": t,
+            "tsigma2_s_mK2": t * (se * 1e3) ** 2}
+
+
+def tsigma(args):
+    """t sigma^2 (Sec. 7.3: time to a given error times that error squared,
+    invariant in the run length) of the GPU path at N=512 (the paper's K20
+    figure is 130 s mK^2 there) and N=2048, and of the oracle on the host
+    cores at N=108 and N=2048."""
+    import torch
+
+    torch.cuda.set_device(0)
+    cores = min(os.cpu_count() or 1, 16)
+    out = {
+        "metric": "t sigma^2 of E/N (time x squared standard error)",
+        "unit": "s mK^2",
+        "n_gpus": 1,
+        "dtype": "f64",
+        "data": "synthetic: fcc-started liquid 4He walkers at 0.02186 / A^3, b = 1.15 sigma",
+        "gpu": [gpu_tsigma(512, 2048, 600, 2000), gpu_tsigma(2048, 512, 400, 1000)],
+        "cpu_baseline": [cpu_baseline_tsigma(108, cores, 400, 2000), cpu_baseline_tsigma(2048, cores, 200, 100)],
+        "cores": cores,
+    }
+    out["value"] = out["gpu"][0]["tsigma2_s_mK2"]
+    print(json.dumps(out), flush=True)
 
 
 def _corr_by_lag(a, b):
@@ -492,6 +627,12 @@ def main():
         return
     if args.replica_decorrelation:
         replica_decorrelation(args)
+        return
+    if args.tsigma:
+        tsigma(args)
+        return
+    if args.c1:
+        c1_run(args)
         return
     if args.precision_check:
         precision_check(args)
