@@ -126,7 +126,30 @@ typedef struct {
     int32_t walkers_per_cu;   /* walkers one compute unit holds at a time                 */
     uint64_t lds_per_walker;  /* LDS bytes of one walker                                  */
     uint64_t lds_per_group;   /* dynamic LDS bytes requested per workgroup                */
+    int32_t slices;           /* workgroups per walker: 1, or C > 1 for a spread walker   */
+    int32_t reserved;         /* 0                                                        */
 } hevmc_plan;
+
+/* Spread walkers.  A walker whose coordinates do not fit in one workgroup's
+ * LDS (FP64 beyond about 6800 atoms, FP32 beyond about 13600) is spread over
+ * C workgroups of a cooperative launch, workgroup g holding atoms
+ * [g S, g S + S): the cooperative kernel that Sec. 3 describes, over several
+ * compute units.  Each micro-update's Eq. (7) sums are formed by the C
+ * workgroups over their own atoms, published to a mailbox in device memory and
+ * added in a fixed order by every workgroup after all C have arrived, so all
+ * take the same Eq. (5) decision; the walker's coordinates in device memory are
+ * the reference copy of positions.  Such walkers use the plain form (no rows;
+ * a rows argument is ignored) with 256 threads per workgroup; their local
+ * energies run in a separate kernel, one workgroup per walker streaming the
+ * coordinates through LDS.  hevmc_init_walkers, hevmc_sweep, hevmc_sweep_log,
+ * hevmc_local_energy, hevmc_footprint, hevmc_plan_launch and the ensemble
+ * layer accept them; the other entry points return HEVMC_ENOFIT.  For spread
+ * walkers hevmc_sweep and hevmc_sweep_log are synchronous: every wait of a
+ * workgroup for the others is bounded, and a wait that gives up (a workgroup
+ * stopped arriving) ends the call with HEVMC_EDEVICE and the walkers' state
+ * not valid.  The library keeps a small device workspace per device for the
+ * mailboxes (grow-only, held until the process ends); calls that overlap on
+ * one device race.  */
 
 /* Fills *out with the launch plan of hevmc_sweep for p.  HEVMC_ENOFIT as
  * hevmc_footprint. */
@@ -135,9 +158,10 @@ hevmc_status hevmc_plan_launch(const hevmc_params *p, hevmc_plan *out);
 /* Box side L = cbrt(n / density) (A), as every kernel uses it. */
 hevmc_status hevmc_box(const hevmc_params *p, double *L_out);
 
-/* LDS bytes one walker's workgroup needs and device bytes an ensemble's state
- * takes (coordinates + accumulators).  HEVMC_ENOFIT if the walker does not fit
- * in one workgroup's LDS on the current device. */
+/* LDS bytes one walker needs (over all its workgroups) and device bytes an
+ * ensemble's state takes (coordinates + accumulators + rows).  HEVMC_ENOFIT if
+ * the walker fits neither one workgroup's LDS nor the chip's as a spread
+ * walker. */
 hevmc_status hevmc_footprint(const hevmc_params *p, size_t *lds_bytes_per_walker,
                              size_t *hbm_bytes);
 

@@ -84,6 +84,8 @@ class Plan(C.Structure):
         ("walkers_per_cu", C.c_int32),
         ("lds_per_walker", C.c_uint64),
         ("lds_per_group", C.c_uint64),
+        ("slices", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 

@@ -51,6 +51,10 @@ C1_SMALL_FP64 = Workload("he4_n108_w1_fp64", 108, 1, FP64, equil=200, measured=1
 C2_N2048_FP64 = Workload("he4_n2048_w512_fp64", 2048, 512, FP64, equil=500, measured=2000, m=5)
 C3_N2048_FP32 = Workload("he4_n2048_w1024_fp32mixed", 2048, 1024, FP32, equil=500, measured=2000, m=5)
 C5_N10976_FP32 = Workload("he4_n10976_w256_fp32mixed", 10976, 256, FP32, equil=200, measured=500, m=5)
+# Walkers beyond one workgroup's LDS, spread over several workgroups (Sec. 3's
+# cooperative kernel across compute units; the paper shows 40960 atoms, Sec. 7).
+SPREAD_N8000_FP64 = Workload("he4_n8000_w128_fp64_spread", 8000, 128, FP64, equil=100, measured=200, m=5)
+SPREAD_N40960_FP32 = Workload("he4_n40960_w64_fp32_spread", 40960, 64, FP32, equil=50, measured=100, m=5)
 
 # Serving stream: N from this set, density U[0.019, 0.026], b U[1.0, 1.3] sigma,
 # 64..512 walkers, run until the standard error of E/N is <= 1 mK.
@@ -61,4 +65,5 @@ SERVE_W = (64, 512)
 SERVE_RATE = 20.0          # requests per second (Poisson)
 SERVE_TARGET_SE = 1.0e-3   # K per atom
 
-ALL = {w.name: w for w in (C1_SMALL_FP64, C2_N2048_FP64, C3_N2048_FP32, C5_N10976_FP32)}
+ALL = {w.name: w for w in (C1_SMALL_FP64, C2_N2048_FP64, C3_N2048_FP32, C5_N10976_FP32, SPREAD_N8000_FP64,
+                            SPREAD_N40960_FP32)}

@@ -173,7 +173,41 @@ void make_kparams(const hevmc_params *p, KParams &k);
 // The request is padded so that each compute unit holds r walkers, r the
 // largest divisor of ceil(W / CUs) whose walkers fit in its LDS: the walkers
 // are then spread evenly over the chip, in equal rounds.
-hevmc_status plan(const hevmc_params *p, void *stream, Launch &L, int32_t gr_bins = 0)
+// A walker whose coordinates do not fit in one workgroup's LDS (spread
+// walker, plain form): C slices of S atoms, one workgroup of 256 threads each,
+// C the fewest slices whose coordinates fit.
+hevmc_status plan_spread(const hevmc_params *p, void *stream, Launch &L, const DeviceLimits &d)
+{
+    const bool fp32 = p->precision == HEVMC_FP32;
+    const size_t tsz = fp32 ? sizeof(float) : sizeof(double);
+    const int threads = 256;
+    const size_t stat = static_lds(threads);
+    const size_t max_dyn = d.lds_per_block > stat ? d.lds_per_block - stat : 0;
+    int C = 2;
+    int S = (p->n + C - 1) / C;
+    while ((size_t)3 * (size_t)S * tsz > max_dyn && C < d.cus) {
+        ++C;
+        S = (p->n + C - 1) / C;
+    }
+    if ((size_t)3 * (size_t)S * tsz > max_dyn)
+        return fail(HEVMC_ENOFIT, "walker of %d atoms does not fit in %d workgroups' LDS", p->n, d.cus);
+    make_kparams(p, L.k);
+    L.k.sorted = 0;
+    L.p.n_walkers_grid = p->n_walkers;
+    L.threads = threads;
+    L.fp32 = fp32;
+    L.rows = false;
+    L.rreg = false;
+    L.spread = true;
+    L.slices = C;
+    L.slice_atoms = S;
+    L.lds_bytes = ((size_t)3 * (size_t)S * tsz + 15) & ~(size_t)15;
+    L.walker_lds = L.lds_bytes * (size_t)C;
+    L.stream = (hipStream_t)stream;
+    return HEVMC_OK;
+}
+
+hevmc_status plan(const hevmc_params *p, void *stream, Launch &L, int32_t gr_bins = 0, bool allow_spread = false)
 {
     hevmc_status st = check_params(p);
     if (st != HEVMC_OK)
@@ -195,9 +229,12 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L, int32_t gr_bin
     const size_t need_plain = lds_needed(p);
     const size_t need_rows = rows_lds_bytes(p);
     const size_t align16 = 15;
-    if (need_plain > max_dyn || (wave_mode && per_group * ((need_plain + align16) & ~align16) > max_dyn))
+    if (need_plain > max_dyn || (wave_mode && per_group * ((need_plain + align16) & ~align16) > max_dyn)) {
+        if (allow_spread && gr_bins == 0 && !wave_mode)
+            return plan_spread(p, stream, L, d);
         return fail(HEVMC_ENOFIT, "walker of %d atoms needs %zu B of LDS; a workgroup can have %zu B", p->n,
                     need_plain * per_group, max_dyn);
+    }
     const bool rows_ok = p->n <= kRowsPerLane * threads &&
                          per_group * ((need_rows + align16) & ~align16) <= max_dyn;
     // rows that do not fit in LDS can live in registers (FP32, 512 threads,
@@ -352,7 +389,7 @@ extern "C" hevmc_status hevmc_plan_launch(const hevmc_params *p, hevmc_plan *out
     if (!out)
         return fail(HEVMC_EINVAL, "out must not be NULL");
     Launch L;
-    hevmc_status st = plan(p, nullptr, L);
+    hevmc_status st = plan(p, nullptr, L, 0, true);
     if (st != HEVMC_OK)
         return st;
     DeviceLimits d;
@@ -362,16 +399,19 @@ extern "C" hevmc_status hevmc_plan_launch(const hevmc_params *p, hevmc_plan *out
     out->threads = L.threads;
     out->variant = L.rows ? HEVMC_VARIANT_ROWS : HEVMC_VARIANT_PLAIN;
     out->spatial_order = L.k.sorted;
-    out->walkers_per_cu = (int32_t)(d.lds_per_cu / (L.lds_bytes + static_lds(L.threads))) * per_group;
+    out->walkers_per_cu =
+        L.spread ? 0 : (int32_t)(d.lds_per_cu / (L.lds_bytes + static_lds(L.threads))) * per_group;
     out->lds_per_walker = L.walker_lds;
     out->lds_per_group = L.lds_bytes;
+    out->slices = L.slices;
+    out->reserved = 0;
     return HEVMC_OK;
 }
 
 extern "C" hevmc_status hevmc_footprint(const hevmc_params *p, size_t *lds_bytes_per_walker, size_t *hbm_bytes)
 {
     Launch L;
-    hevmc_status st = plan(p, nullptr, L);
+    hevmc_status st = plan(p, nullptr, L, 0, true);
     if (st != HEVMC_OK)
         return st;
     if (lds_bytes_per_walker)
@@ -386,13 +426,20 @@ extern "C" hevmc_status hevmc_init_walkers(const hevmc_params *p, void *coords, 
                                            double *rows, int32_t fcc_start, void *stream)
 {
     Launch L;
-    hevmc_status st = plan(p, stream, L);
+    hevmc_status st = plan(p, stream, L, 0, true);
     if (st != HEVMC_OK)
         return st;
     if (!coords || !acc)
         return fail(HEVMC_EINVAL, "coords and acc must be device pointers");
     int nc;
     fcc_cells(p->n, nc);
+    if (L.spread) {
+        // spread walkers keep no rows (plain form)
+        if (fcc_start && (st = launched(launch_fcc_global(L, coords, nc, L.k.L / nc), "fcc kernel launch")) !=
+                             HEVMC_OK)
+            return st;
+        return launched(launch_energy_global(L, coords, acc, nullptr, 0), "start kernel launch");
+    }
     return launched(launch_init(L, coords, acc, rows, fcc_start ? 1 : 0, nc, L.k.L / nc), "init kernel launch");
 }
 
@@ -413,6 +460,143 @@ struct MoveLog {
     int64_t cap = 0;
 };
 
+// Device workspace of the cooperative sweeps (mailboxes, arrival counters,
+// status word): one grow-only buffer per device, kept until the process ends.
+// Calls that overlap on one device would share it: they race (as calls that
+// share buffers do).
+static hevmc_status spread_workspace(size_t bytes, void **out)
+{
+    static std::mutex mu;
+    static std::map<int, std::pair<void *, size_t>> bufs;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> g(mu);
+    auto &b = bufs[dev];
+    if (b.second < bytes) {
+        if (b.first) {
+            e = hipDeviceSynchronize();
+            if (e != hipSuccess)
+                return hip_fail(e, "workspace release");
+            (void)hipFree(b.first);
+            b.first = nullptr;
+            b.second = 0;
+        }
+        e = hipMalloc(&b.first, bytes);
+        if (e != hipSuccess)
+            return fail(HEVMC_ENOMEM, "hipMalloc of %zu B for the cooperative sweep's workspace failed", bytes);
+        b.second = bytes;
+    }
+    *out = b.first;
+    return HEVMC_OK;
+}
+
+// Polls a cooperative sweep's wait makes before it gives up: HEVMC_SPREAD_SPIN_CAP
+// from the environment if set (tests force timeouts with it), else 2^22.
+static uint32_t spread_spin_cap()
+{
+    const char *v = getenv("HEVMC_SPREAD_SPIN_CAP");
+    if (v && *v) {
+        char *end = nullptr;
+        const unsigned long x = strtoul(v, &end, 10);
+        if (end && *end == 0)
+            return (uint32_t)std::min<unsigned long>(x, 0xFFFFFFFFul);
+    }
+    return 1u << 22;
+}
+
+// hevmc_sweep of spread walkers: groups of walkers that the chip holds at
+// once (every workgroup of a cooperative launch must be resident), each group
+// in launches that end at the local-energy samples, which run between them.
+// Waits for the stream and reports a wait that gave up as HEVMC_EDEVICE.
+static hevmc_status sweep_spread(const Launch &L, const hevmc_params *p, void *coords, hevmc_walker_acc *acc,
+                                 uint32_t sweep0, int32_t n_sweeps, uint32_t mstart, int32_t m, const MoveLog &mlog)
+{
+    DeviceLimits d;
+    hevmc_status st = device_limits(d);
+    if (st != HEVMC_OK)
+        return st;
+    int bpc = 0;
+    if ((st = launched(coop_blocks_per_cu(L, &bpc), "cooperative occupancy query")) != HEVMC_OK)
+        return st;
+    const int C = L.slices;
+    const int max_group = bpc * d.cus / C;
+    if (max_group < 1)
+        return fail(HEVMC_ENOFIT, "a walker of %d slices does not fit on the chip at once", C);
+    const int W = p->n_walkers, G = std::min(W, max_group);
+    const size_t mail_bytes = (size_t)G * 4 * (size_t)C * sizeof(double);
+    const size_t bytes = mail_bytes + (size_t)G * sizeof(uint32_t) + 64;
+    void *ws = nullptr;
+    if ((st = spread_workspace(bytes, &ws)) != HEVMC_OK)
+        return st;
+    CoopArgs c;
+    c.mail = static_cast<double *>(ws);
+    c.arrive = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + mail_bytes);
+    c.status = c.arrive + G;
+    c.spin_cap = spread_spin_cap();
+    c.C = C;
+    c.S = L.slice_atoms;
+    hipError_t e = hipMemsetAsync(c.status, 0, sizeof(uint32_t), L.stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "status reset");
+    const size_t tsz = L.fp32 ? sizeof(float) : sizeof(double);
+    const size_t per_walker = (size_t)3 * (size_t)p->n * tsz;
+    const uint64_t end = (uint64_t)sweep0 + (uint64_t)n_sweeps;
+    for (int w0 = 0; w0 < W; w0 += G) {
+        const int g = std::min(G, W - w0);
+        Launch Lg = L;
+        Lg.p.n_walkers_grid = g;
+        Lg.k.wid_base = L.k.wid_base + (uint32_t)w0;
+        if (mlog.log && w0 < mlog.walkers) {
+            Lg.k.movelog = mlog.log + (size_t)w0 * (size_t)mlog.cap * 4;
+            Lg.k.log_walkers = mlog.walkers - w0;
+            Lg.k.log_cap = mlog.cap;
+        } else {
+            Lg.k.movelog = nullptr;
+            Lg.k.log_walkers = 0;
+        }
+        void *cg = static_cast<char *>(coords) + (size_t)w0 * per_walker;
+        hevmc_walker_acc *ag = acc + w0;
+        uint64_t t = sweep0;
+        while (t < end) {
+            // the launch runs to the next sampled sweep (inclusive) or to the end
+            uint64_t te = end - 1;
+            bool sample = false;
+            if (m > 0 && mstart != 0xFFFFFFFFu) {
+                const uint64_t first = std::max<uint64_t>(t, mstart);
+                const uint64_t k = (first - mstart + (uint64_t)m) / (uint64_t)m;   // ceil((first - mstart + 1) / m)
+                const uint64_t ts = mstart + k * (uint64_t)m - 1;
+                if (ts < end) {
+                    te = ts;
+                    sample = true;
+                }
+            }
+            c.log_base = (int64_t)(t - sweep0) * p->n;
+            e = hipMemsetAsync(c.arrive, 0, (size_t)g * sizeof(uint32_t), L.stream);
+            if (e != hipSuccess)
+                return hip_fail(e, "arrival counter reset");
+            if ((st = launched(launch_sweep_coop(Lg, c, cg, ag, (uint32_t)t, (int32_t)(te - t + 1), mstart, g),
+                               "cooperative sweep launch")) != HEVMC_OK)
+                return st;
+            if (sample && (st = launched(launch_energy_global(Lg, cg, ag, nullptr, 1), "sample kernel launch")) !=
+                              HEVMC_OK)
+                return st;
+            t = te + 1;
+        }
+    }
+    uint32_t status = 0;
+    e = hipMemcpyAsync(&status, c.status, sizeof(uint32_t), hipMemcpyDeviceToHost, L.stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(L.stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "cooperative sweep");
+    if (status)
+        return fail(HEVMC_EDEVICE, "a cooperative sweep's wait gave up after %u polls (a workgroup of a walker "
+                    "stopped arriving); the walkers' state is not valid", c.spin_cap);
+    return HEVMC_OK;
+}
+
 // The sweep with its optional outputs: pair histogram, per-sample trace and
 // per-move records.
 static hevmc_status sweep_with(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
@@ -425,7 +609,7 @@ static hevmc_status sweep_with(const hevmc_params *p, void *coords, hevmc_walker
     if (trace && trace_cap < 1)
         return fail(HEVMC_EINVAL, "trace_cap = %d must be >= 1", trace_cap);
     Launch L;
-    hevmc_status st = plan(p, stream, L, gr ? gr_bins : 0);
+    hevmc_status st = plan(p, stream, L, gr ? gr_bins : 0, !gr && !trace);
     if (st != HEVMC_OK)
         return st;
     L.k.gr = gr;
@@ -450,6 +634,8 @@ static hevmc_status sweep_with(const hevmc_params *p, void *coords, hevmc_walker
         return fail(HEVMC_EINVAL, "sweep counter would pass 2^32 - 1");
     if (n_sweeps == 0)
         return HEVMC_OK;
+    if (L.spread)
+        return sweep_spread(L, p, coords, acc, sweep0, n_sweeps, measure_start, energy_every, mlog);
     L.k.share_tag = shares_cu(L) ? next_share_tag() : 0u;
     return launched(launch_sweep(L, coords, acc, rows, sweep0, n_sweeps, measure_start, energy_every),
                     "sweep kernel launch");
@@ -552,11 +738,13 @@ extern "C" hevmc_status hevmc_sweep_batch(int32_t n_requests, const hevmc_reques
 extern "C" hevmc_status hevmc_local_energy(const hevmc_params *p, const void *coords, double *out, void *stream)
 {
     Launch L;
-    hevmc_status st = plan(p, stream, L);
+    hevmc_status st = plan(p, stream, L, 0, true);
     if (st != HEVMC_OK)
         return st;
     if (!coords || !out)
         return fail(HEVMC_EINVAL, "coords and out must be device pointers");
+    if (L.spread)
+        return launched(launch_energy_global(L, coords, nullptr, out, 2), "local-energy kernel launch");
     return launched(launch_local_energy(L, coords, out), "local-energy kernel launch");
 }
 
@@ -660,7 +848,7 @@ extern "C" hevmc_status hevmc_create(const hevmc_params *p, const double *init_x
                                      hevmc_ensemble **out)
 {
     Launch L;
-    hevmc_status st = plan(p, stream, L);
+    hevmc_status st = plan(p, stream, L, 0, true);
     if (st != HEVMC_OK)
         return st;
     if (!out)
@@ -714,7 +902,7 @@ extern "C" hevmc_status hevmc_create_on(const hevmc_params *p, void *dev_coords,
                                         void *stream, hevmc_ensemble **out)
 {
     Launch L;
-    hevmc_status st = plan(p, stream, L);
+    hevmc_status st = plan(p, stream, L, 0, true);
     if (st != HEVMC_OK)
         return st;
     if (!out || !dev_coords || !dev_acc)

@@ -71,6 +71,21 @@ struct BatchArgs {
     int32_t count;
 };
 
+// The mailbox of a cooperative sweep of spread walkers (walkers whose
+// coordinates do not fit in one workgroup's LDS): per walker, the partial
+// Eq. (7) sums of its C slices for the two parities of the micro-update
+// counter ([W][2][C][2] doubles) and an arrival counter ([W], zero at launch);
+// status becomes nonzero if a wait gave up after spin_cap polls.
+struct CoopArgs {
+    double *mail;
+    uint32_t *arrive;
+    uint32_t *status;
+    uint32_t spin_cap;
+    int32_t C;          // workgroups (slices) per walker
+    int32_t S;          // atoms per slice (the last may hold fewer)
+    int64_t log_base;   // per-move records: micro-updates of the call before this launch
+};
+
 struct LaunchShape {
     int n_walkers_grid;  // workgroups (walkers) in the grid
 };
@@ -86,6 +101,9 @@ struct Launch {
     size_t lds_bytes;   // dynamic LDS per workgroup of the sweep kernel
     size_t walker_lds;  // dynamic LDS of one walker (the per-walker kernels)
     hipStream_t stream;
+    bool spread = false;  // the walker does not fit in one workgroup's LDS: C slices
+    int slices = 1;       // C
+    int slice_atoms = 0;  // S
 };
 
 hipError_t launch_sweep(const Launch &L, void *coords, hevmc_walker_acc *acc, double *rows, uint32_t sweep0,
@@ -99,6 +117,15 @@ hipError_t launch_init(const Launch &L, void *coords, hevmc_walker_acc *acc, dou
 hipError_t launch_move_delta(const Launch &L, const void *coords, const int32_t *s, const double *d,
                              double *out);
 hipError_t launch_draw_moves(const Launch &L, uint32_t t, int32_t *s, double *xi, double *d);
+// Spread walkers: the cooperative sweep of `walkers` walkers from coords and
+// acc (already offset), the one-workgroup-per-walker local energy in device
+// memory (mode 0 start, 1 sample, 2 values to out), the fcc start, and the
+// cooperative kernel's workgroups per compute unit.
+hipError_t launch_sweep_coop(const Launch &L, const CoopArgs &c, void *coords, hevmc_walker_acc *acc,
+                             uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t walkers);
+hipError_t launch_energy_global(const Launch &L, const void *coords, hevmc_walker_acc *acc, double *out, int mode);
+hipError_t launch_fcc_global(const Launch &L, void *coords, int nc, double a_lat);
+hipError_t coop_blocks_per_cu(const Launch &L, int *blocks_per_cu);
 
 // Registers per thread and static LDS bytes of the sweep kernel for
 // (precision, threads, variant); zeros if unknown.

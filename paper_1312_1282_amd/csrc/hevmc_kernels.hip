@@ -1526,6 +1526,386 @@ hipError_t launch_move_delta(const Launch &L, const void *coords, const int32_t 
     HEVMC_DISPATCH(launch_delta_t, coords, s, d, out);
 }
 
+// ---------------------------------------------------------------------------
+// Walkers beyond one workgroup's LDS ("spread" walkers).  Sec. 3 describes a
+// cooperative kernel in which several blocks serve one walker; here one
+// walker is spread over C workgroups of a cooperative launch (every
+// workgroup resident at once), workgroup g holding atoms [g S, g S + S) of
+// the walker in its LDS.  Every micro-update is decided by all C workgroups
+// together: each forms the Eq. (7) sums over its own atoms (the plain form:
+// u and V at the old and the new position), publishes them to a mailbox in
+// device memory, and waits until all C have arrived; every workgroup then
+// adds the C partial sums in the same order and takes the same decision.
+// The walker's coordinates in device memory are the reference copy: the
+// owner of an accepted atom writes its new position there, and the others
+// read old positions of atoms outside their slice from it.  Every wait is
+// bounded: after spin_cap polls the workgroup gives up, records the timeout
+// in *status and leaves; the others then time out in turn, so the grid
+// always drains.  Local energies of such walkers come from a separate kernel
+// with one workgroup per walker that streams the partners through LDS tiles.
+
+// Local energy terms (or just the running totals U, V) of walker blockIdx.x,
+// with the coordinates read from device memory in tiles of `tile` atoms.
+// mode 0: start (u_run, v_run of the configuration; accumulators zeroed);
+// mode 1: a sample (accumulators, u_run, v_run reset to the fresh totals);
+// mode 2: write (E_L, V, T_PB, T_JF, T_F, U) to out[blockIdx.x][6].
+// Every ordered pair is formed: V and U are halved, and the Laplacian and
+// gradient terms of atom i run over all its partners.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_energy_global(KParams p, const T *__restrict__ coords,
+                                                      hevmc_walker_acc *__restrict__ accs, double *__restrict__ out,
+                                                      int mode, int tile)
+{
+    constexpr int NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double ebuf[NW * 4];
+    T *tx = reinterpret_cast<T *>(smem_raw);
+    T *ty = tx + tile, *tz = ty + tile;
+    const int n = p.n, tid = threadIdx.x;
+    const T *gx = coords + (size_t)blockIdx.x * 3 * (size_t)n;
+    const T *gy = gx + n, *gz = gy + n;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};   // sum |G_i|^2, sum L_i, ordered V, ordered U
+    bool bad = false;
+    for (int c0 = 0; c0 < n; c0 += NT) {
+        const int i = c0 + tid;
+        const bool live = i < n;
+        const T xi = live ? gx[i] : T(0), yi = live ? gy[i] : T(0), zi = live ? gz[i] : T(0);
+        bad |= live && !(isfinite((double)xi) && isfinite((double)yi) && isfinite((double)zi));
+        double sgx = 0.0, sgy = 0.0, sgz = 0.0, sl = 0.0, sv = 0.0, su = 0.0;
+        for (int j0 = 0; j0 < n; j0 += tile) {
+            const int m = min(tile, n - j0);
+            __syncthreads();
+            for (int q = tid; q < m; q += NT) {
+                tx[q] = gx[j0 + q];
+                ty[q] = gy[j0 + q];
+                tz[q] = gz[j0 + q];
+            }
+            __syncthreads();
+            for (int q = 0; q < m; ++q) {
+                if (!live || j0 + q == i)
+                    continue;
+                const T dx = min_image(xi - tx[q], p);
+                const T dy = min_image(yi - ty[q], p);
+                const T dz = min_image(zi - tz[q], p);
+                ETerms e;
+                pair_energy(p, dx * dx + dy * dy + dz * dz, e);
+                sgx += e.dur * (double)dx;
+                sgy += e.dur * (double)dy;
+                sgz += e.dur * (double)dz;
+                sl += e.lap;
+                sv += e.v;
+                su += e.u;
+            }
+        }
+        acc[0] += sgx * sgx + sgy * sgy + sgz * sgz;
+        acc[1] += sl;
+        acc[2] += sv;
+        acc[3] += su;
+    }
+    const bool any_bad = walker_any<NT>(bad, ebuf);
+    block_sum<NT, 4>(acc, ebuf);
+    if (tid != 0)
+        return;
+    const double V = 0.5 * acc[2], U = 0.5 * acc[3];
+    const double tpb = -p.kappa * (acc[1] + acc[0]);
+    const double el[6] = {V + tpb, V, tpb, -0.5 * p.kappa * acc[1], p.kappa * acc[0], U};
+    if (mode == 2) {
+        for (int q = 0; q < 6; ++q)
+            out[(size_t)blockIdx.x * 6 + q] = el[q];
+        return;
+    }
+    hevmc_walker_acc *a = accs + blockIdx.x;
+    if (mode == 0) {
+        hevmc_walker_acc z = {};
+        *a = z;
+    } else {
+        nsum(a->sum_e, a->c_e, el[0]);
+        nsum(a->sum_e2, a->c_e2, el[0] * el[0]);
+        nsum(a->sum_v, a->c_v, el[1]);
+        nsum(a->sum_tpb, a->c_tpb, el[2]);
+        nsum(a->sum_tjf, a->c_tjf, el[3]);
+        nsum(a->sum_tf, a->c_tf, el[4]);
+        a->n_samples += 1;
+    }
+    a->u_run = any_bad ? __builtin_nan("") : U;
+    a->v_run = any_bad ? __builtin_nan("") : V;
+}
+
+// fcc start of spread walkers, one thread per atom (as k_init's fcc start).
+template <typename T>
+__global__ void k_fcc_global(KParams p, T *__restrict__ coords, int n_walkers, int nc, double a_lat)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = p.n;
+    if (q >= (int64_t)n_walkers * n)
+        return;
+    const int w = (int)(q / n), i = (int)(q % n);
+    T *g = coords + (size_t)w * 3 * (size_t)n;
+    fcc_site<T>(p, p.wid_base + (uint32_t)w, i, nc, a_lat, &g[i], &g[n + i], &g[2 * n + i]);
+}
+
+// The cooperative sweep of spread walkers: workgroup blockIdx.x serves slice
+// g = blockIdx.x % c.C of walker blockIdx.x / c.C.  Sweeps t = sweep0 ..
+// sweep0 + nsw - 1, the plain form of Eq. (7) (u and V at both positions),
+// no local-energy samples (the caller runs them between launches); measured
+// sweeps count moves and add v_run to sum_vs.  Movelog as in k_sweep.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_sweep_coop(KParams p, CoopArgs c, T *__restrict__ coords,
+                                                   hevmc_walker_acc *__restrict__ accs, uint32_t sweep0,
+                                                   int32_t nsw, uint32_t mstart)
+{
+    constexpr int NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[NW][2];
+    __shared__ double tot[2];
+    __shared__ int fail_flag;
+    const int w = (int)(blockIdx.x / (uint32_t)c.C), g = (int)(blockIdx.x % (uint32_t)c.C);
+    const int n = p.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i0 = g * c.S, ns = min(c.S, n - i0);   // this workgroup's atoms [i0, i0 + ns)
+    T *gx = coords + (size_t)w * 3 * (size_t)n;
+    T *gy = gx + n, *gz = gy + n;
+    T *sx = reinterpret_cast<T *>(smem_raw);
+    T *sy = sx + c.S, *sz = sy + c.S;
+    for (int i = tid; i < ns; i += NT) {
+        sx[i] = gx[i0 + i];
+        sy[i] = gy[i0 + i];
+        sz[i] = gz[i0 + i];
+    }
+    if (tid == 0)
+        fail_flag = 0;
+    __syncthreads();
+    hevmc_walker_acc *accp = accs + w;
+    double u_run = accp->u_run, v_run = accp->v_run;
+    int64_t n_acc = 0, n_try = 0, n_swm = 0;
+    const uint32_t wid = p.wid_base + (uint32_t)w;
+    double *mail = c.mail + (size_t)w * 4 * (size_t)c.C;
+    uint32_t *arrive = c.arrive + w;
+    double *mlw = (p.movelog && w < p.log_walkers && g == 0) ? p.movelog + (size_t)w * (size_t)p.log_cap * 4
+                                                             : nullptr;
+    uint32_t mv = 0;          // micro-updates of this launch
+    int last_s = -1;          // atom accepted in the previous micro-update
+    T lx = 0, ly = 0, lz = 0; // its new position
+    bool failed = false;
+    for (int it = 0; it < nsw && !failed; ++it) {
+        const uint32_t t = sweep0 + (uint32_t)it;
+        const bool measured = t >= mstart;
+        for (int k0 = 0; k0 < n && !failed; k0 += 64) {
+            int bs;
+            double bxi, bdx, bdy, bdz;
+            draw_move(p, (uint32_t)(k0 + lane), t, wid, bs, bxi, bdx, bdy, bdz);
+            const double blx = log(bxi);
+            // old and trial positions of the batch from the reference copy
+            // (current for every atom but the one accepted just before: its
+            // micro-update's barrier-free write may not be seen yet)
+            const T bnx = trial_coord<T>((double)gx[bs] + bdx, p);
+            const T bny = trial_coord<T>((double)gy[bs] + bdy, p);
+            const T bnz = trial_coord<T>((double)gz[bs] + bdz, p);
+            uint64_t stale = last_s >= 0 ? __builtin_amdgcn_ballot_w64(bs == last_s) : 0ull;
+            const int kend = min(64, n - k0);
+            for (int j = 0; j < kend; ++j) {
+                const int s = readlane_i(bs, j);
+                const double lxi = lane_value(blx, j);
+                T ox, oy, oz, nx, ny, nz;
+                if (s == last_s) {
+                    ox = lx; oy = ly; oz = lz;
+                } else {
+                    ox = gx[s]; oy = gy[s]; oz = gz[s];
+                }
+                if ((stale >> j) & 1ull) {
+                    nx = trial_coord<T>((double)ox + lane_value(bdx, j), p);
+                    ny = trial_coord<T>((double)oy + lane_value(bdy, j), p);
+                    nz = trial_coord<T>((double)oz + lane_value(bdz, j), p);
+                } else {
+                    nx = lane_value(bnx, j); ny = lane_value(bny, j); nz = lane_value(bnz, j);
+                }
+                // this workgroup's part of the Eq. (7) sums
+                double du = 0.0, dv = 0.0;
+                for (int q = tid; q < ns; q += NT) {
+                    const T xi = sx[q], yi = sy[q], zi = sz[q];
+                    const T r2o = dist2(p, ox, oy, oz, xi, yi, zi);
+                    const T r2n = dist2(p, nx, ny, nz, xi, yi, zi);
+                    T uo, vo, un, vn;
+                    pair_uv(p, r2o, uo, vo);
+                    pair_uv(p, r2n, un, vn);
+                    const bool self = (i0 + q == s);
+                    du += self ? 0.0 : (double)(un - uo);
+                    dv += self ? 0.0 : (double)(vn - vo);
+                }
+                du = wave_sum(du);
+                dv = wave_sum(dv);
+                if (lane == 0) {
+                    red[wave][0] = du;
+                    red[wave][1] = dv;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    double pu = 0.0, pv = 0.0;
+                    for (int q = 0; q < NW; ++q) {
+                        pu += red[q][0];
+                        pv += red[q][1];
+                    }
+                    double *slot = mail + ((size_t)(mv & 1u) * c.C + g) * 2;
+                    slot[0] = pu;
+                    slot[1] = pv;
+                    __threadfence();
+                    atomicAdd(arrive, 1u);
+                    const uint32_t target = (mv + 1u) * (uint32_t)c.C;
+                    uint32_t spins = 0;
+                    int f = 0;
+                    while (__hip_atomic_load(arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                        if (++spins > c.spin_cap) {
+                            f = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    __threadfence();
+                    double DU = 0.0, DV = 0.0;
+                    const double *row = mail + (size_t)(mv & 1u) * c.C * 2;
+                    for (int q = 0; q < c.C; ++q) {
+                        DU += __hip_atomic_load(row + 2 * q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        DV += __hip_atomic_load(row + 2 * q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    tot[0] = DU;
+                    tot[1] = DV;
+                    fail_flag = f;
+                }
+                __syncthreads();
+                if (fail_flag) {
+                    failed = true;
+                    break;
+                }
+                const double DU = tot[0], DV = tot[1];
+                ++mv;
+                const bool accept = metropolis_accept_log(DU, lxi);
+                const int64_t q_log = c.log_base + (int64_t)it * n + k0 + j;
+                if (mlw && tid == 0 && q_log < p.log_cap) {
+                    double *rec = mlw + 4 * q_log;
+                    rec[0] = (double)s;
+                    rec[1] = accept ? 1.0 : 0.0;
+                    rec[2] = DU;
+                    rec[3] = DV;
+                }
+                if (measured) {
+                    n_try += 1;
+                    n_acc += accept ? 1 : 0;
+                }
+                if (accept) {
+                    u_run += DU;
+                    v_run += DV;
+                    if (s >= i0 && s < i0 + ns && tid == (s - i0) % NT) {
+                        sx[s - i0] = nx; sy[s - i0] = ny; sz[s - i0] = nz;
+                        gx[s] = nx; gy[s] = ny; gz[s] = nz;
+                    }
+                    const uint64_t later = j >= 63 ? 0ull : (~0ull << (j + 1));
+                    stale |= __builtin_amdgcn_ballot_w64(bs == s) & later;
+                    last_s = s;
+                    lx = nx; ly = ny; lz = nz;
+                } else {
+                    last_s = -1;
+                }
+            }
+        }
+        if (measured && !failed) {
+            if (g == 0 && tid == 0)
+                nsum(accp->sum_vs, accp->c_vs, v_run);
+            n_swm += 1;
+        }
+    }
+    if (failed) {
+        if (tid == 0)
+            atomicOr(c.status, 1u);
+        return;
+    }
+    if (g == 0 && tid == 0) {
+        accp->u_run = u_run;
+        accp->v_run = v_run;
+        accp->n_sweeps_meas += n_swm;
+        accp->n_acc += n_acc;
+        accp->n_try += n_try;
+    }
+}
+
+template <typename T, int NT>
+static hipError_t launch_coop_t(const Launch &L, const CoopArgs &c, void *coords, hevmc_walker_acc *acc,
+                                uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t walkers)
+{
+    if constexpr (NT != 256) {
+        return hipErrorInvalidValue;
+    } else {
+        auto kern = k_sweep_coop<T, NT>;
+        hipError_t e = allow_lds(kern, L.lds_bytes);
+        if (e != hipSuccess)
+            return e;
+        KParams k = L.k;
+        CoopArgs ca = c;
+        T *cp = (T *)coords;
+        void *args[] = {&k, &ca, &cp, &acc, &sweep0, &nsw, &mstart};
+        return hipLaunchCooperativeKernel((const void *)kern, dim3((unsigned)(walkers * c.C)), dim3(NT), args,
+                                          (unsigned)L.lds_bytes, L.stream);
+    }
+}
+
+template <typename T, int NT>
+static hipError_t coop_capacity_t(const Launch &L, int *blocks_per_cu)
+{
+    if constexpr (NT != 256) {
+        return hipErrorInvalidValue;
+    } else {
+        auto kern = k_sweep_coop<T, NT>;
+        hipError_t e = allow_lds(kern, L.lds_bytes);
+        if (e != hipSuccess)
+            return e;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)kern, NT, L.lds_bytes);
+    }
+}
+
+template <typename T, int NT>
+static hipError_t launch_energy_global_t(const Launch &L, const void *coords, hevmc_walker_acc *acc, double *out,
+                                         int mode, int tile)
+{
+    auto kern = k_energy_global<T, NT>;
+    const size_t lds = 3 * (size_t)tile * sizeof(T);
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), lds, L.stream, L.k, (const T *)coords, acc, out,
+                       mode, tile);
+    return hipGetLastError();
+}
+
+template <typename T, int NT>
+static hipError_t launch_fcc_global_t(const Launch &L, void *coords, int nc, double a_lat)
+{
+    const int64_t total = (int64_t)L.p.n_walkers_grid * L.k.n;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_fcc_global<T>, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, L.stream, L.k,
+                       (T *)coords, L.p.n_walkers_grid, nc, a_lat);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_coop(const Launch &L, const CoopArgs &c, void *coords, hevmc_walker_acc *acc,
+                             uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t walkers)
+{
+    HEVMC_DISPATCH(launch_coop_t, c, coords, acc, sweep0, nsw, mstart, walkers);
+}
+
+hipError_t coop_blocks_per_cu(const Launch &L, int *blocks_per_cu)
+{
+    HEVMC_DISPATCH(coop_capacity_t, blocks_per_cu);
+}
+
+hipError_t launch_energy_global(const Launch &L, const void *coords, hevmc_walker_acc *acc, double *out, int mode)
+{
+    const int tile = L.fp32 ? 4096 : 2048;
+    HEVMC_DISPATCH(launch_energy_global_t, coords, acc, out, mode, tile);
+}
+
+hipError_t launch_fcc_global(const Launch &L, void *coords, int nc, double a_lat)
+{
+    HEVMC_DISPATCH(launch_fcc_global_t, coords, nc, a_lat);
+}
+
 hipError_t launch_draw_moves(const Launch &L, uint32_t t, int32_t *s, double *xi, double *d)
 {
     const int total = L.p.n_walkers_grid * L.k.n;

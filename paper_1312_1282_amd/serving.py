@@ -182,7 +182,11 @@ class Server:
 
     # -- footprint ---------------------------------------------------------
     def footprint(self, req):
-        lds, hbm = abi.footprint(self.params(req))
+        p = self.params(req)
+        if abi.plan_launch(p)["slices"] > 1:
+            # a walker spread over several workgroups has no batched sweep
+            raise abi.HevmcError(-3, f"walker of {req.n} atoms does not fit in one workgroup's LDS")
+        lds, hbm = abi.footprint(p)
         return lds * req.walkers, hbm
 
     def _pool(self, req, torch):

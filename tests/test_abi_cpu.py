@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 def test_parameter_struct_layouts():
     assert C.sizeof(abi.Params) == 72
     assert C.sizeof(abi.WalkerAcc) == 160
-    assert C.sizeof(abi.Plan) == 32
+    assert C.sizeof(abi.Plan) == 40
 
 
 @pytest.mark.parametrize("bad", [

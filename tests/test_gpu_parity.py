@@ -115,20 +115,24 @@ def test_invalid_move_index_gives_nan_and_eval_rejects():
 
 
 def test_fp64_walker_too_large_for_lds():
+    """An FP64 walker of 10976 atoms (263 KB) fits in no workgroup's LDS: the
+    plan spreads it over two workgroups, and the entry points without a
+    spread form refuse it."""
+    p = gparams(10976, 1)
+    plan = abi.plan_launch(p)
+    assert plan["slices"] == 2 and plan["variant"] == abi.VARIANT_PLAIN
+    lds, _ = abi.footprint(p)
+    assert lds == 2 * plan["lds_per_group"]
+    coords, acc = abi.alloc_state(p)
     with pytest.raises(abi.HevmcError) as ei:
-        abi.footprint(gparams(10976, 1))
+        abi.pair_histogram(p, coords, torch.zeros((1, 16), dtype=torch.int64, device="cuda"))
     assert ei.value.code == -3
 
 
 def _largest_fitting_n(precision, lo, hi):
     """Largest N whose walker fits one workgroup's LDS (bisection on the plan)."""
     def fits(n):
-        try:
-            abi.footprint(gparams(n, 1, precision=precision))
-            return True
-        except abi.HevmcError as e:
-            assert e.code == -3
-            return False
+        return abi.plan_launch(gparams(n, 1, precision=precision))["slices"] == 1
     assert fits(lo) and not fits(hi)
     while hi - lo > 1:
         mid = (lo + hi) // 2
@@ -137,11 +141,12 @@ def _largest_fitting_n(precision, lo, hi):
 
 
 def test_largest_fp64_walker_follows_the_oracle():
-    """The largest FP64 walker that fits in LDS (plain variant, about 6800
-    atoms): one sweep with a local-energy sample, against the oracle; one
-    atom more is refused."""
+    """The largest FP64 walker that fits in one workgroup's LDS (plain
+    variant, about 6800 atoms): one sweep with a local-energy sample, against
+    the oracle; one atom more is spread over two workgroups."""
     n = _largest_fitting_n(abi.FP64, 4000, 10976)
     assert 6000 < n < 7000
+    assert abi.plan_launch(gparams(n + 1, 1))["slices"] == 2
     p = gparams(n, 2, seed=12)
     plan = abi.plan_launch(p)
     assert plan["variant"] == abi.VARIANT_PLAIN and plan["lds_per_walker"] >= 24 * n

@@ -1,0 +1,150 @@
+"""Spread walkers: one walker over several workgroups of a cooperative launch
+(the cooperative kernel of Sec. 3, across compute units), for walkers whose
+coordinates fit in no workgroup's LDS.  Held to the oracle like the
+single-workgroup sweep:
+
+  * start and local energy: FP64 values within 1e-12 of the oracle's scale;
+  * every micro-update of an FP64 sweep (plain form: dU and dV of every move)
+    in lockstep with the oracle's own chain, at 1e-12 of the summed
+    magnitudes, and the sample that ends it;
+  * an FP32 walker beyond one workgroup (coordinates in FP32) move by move
+    within the FP32 bounds, up to the first decision that rounding could flip;
+  * a wait that gives up (forced from the host by a zero poll limit) ends
+    the call with HEVMC_EDEVICE, every workgroup having left the kernel, and
+    the library works normally afterwards.
+"""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1312_1282_amd import abi, configs
+from test_gpu_movelog import compare_fp32, compare_fp64, _xi_logs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RHO = configs.RHO_EQ
+B = configs.C1_SMALL_FP64.b
+STEP = configs.C1_SMALL_FP64.step_sigma
+
+
+def params(n, W, precision=abi.FP64, seed=17):
+    return abi.make_params(n, W, precision=precision, density=RHO, b=B, step_sigma=STEP, seed=seed)
+
+
+def osys(n, seed=17, fp32=False):
+    return O.system(n, O.box_side(n, RHO, fp32), B, hbar2_over_m=configs.HBAR2_OVER_M, step_sigma=STEP,
+                    seed=seed, fp32_coords=fp32)
+
+
+def test_spread_plans():
+    p = params(8000, 2)
+    plan = abi.plan_launch(p)
+    assert (plan["slices"], plan["threads"], plan["variant"], plan["spatial_order"]) == (2, 256, abi.VARIANT_PLAIN, 0)
+    assert plan["lds_per_group"] >= 3 * 4000 * 8 and plan["lds_per_group"] <= 160 * 1024
+    assert abi.plan_launch(params(14000, 1, abi.FP32))["slices"] == 2
+    assert abi.plan_launch(params(2048, 1))["slices"] == 1
+    assert abi.plan_launch(params(13000, 1, abi.FP32))["slices"] == 1   # rows in registers, one workgroup
+
+
+def test_spread_start_and_local_energy_follow_the_oracle():
+    n, W = 8000, 2
+    p = params(n, W)
+    coords, acc = abi.alloc_state(p)
+    abi.init_walkers(p, coords, acc, fcc_start=True)
+    out = torch.zeros((W, 6), dtype=torch.float64, device="cuda")
+    abi.local_energy(p, coords, out)
+    torch.cuda.synchronize()
+    xs = coords.cpu().numpy()
+    a = abi.acc_to_numpy(acc)
+    el_g = out.cpu().numpy()
+    s_ = osys(n)
+    for w in range(W):
+        ref = O.fcc_start(s_, w)
+        assert np.max(np.abs(xs[w] - ref)) <= 1e-13 * s_.L
+        el, scale = O.local_energy(s_, xs[w])
+        assert np.all(np.abs(el_g[w] - el) <= 1e-12 * scale), (el_g[w], el)
+        U, V = el[5], el[1]
+        assert a["u_run"][w] == pytest.approx(U, rel=1e-12)
+        assert a["v_run"][w] == pytest.approx(V, rel=1e-12)
+        assert a["n_try"][w] == 0 and a["sum_e"][w] == 0
+
+
+def _oracle_logs(s_, walkers, n_sweeps, measure_start, m):
+    res = {}
+
+    def work(w):
+        x = O.fcc_start(s_, w)
+        a = O.walker_init(s_, x)
+        res[w] = (O.run_walker_log(s_, w, x, a, 0, n_sweeps, measure_start, m), a, x)
+
+    th = [threading.Thread(target=work, args=(w,)) for w in walkers]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    return res
+
+
+def test_spread_every_move_follows_the_oracle_fp64():
+    """N = 8000 in FP64 (192 KB of coordinates, two workgroups), two walkers,
+    one measured sweep with the local-energy sample that ends it."""
+    n, W = 8000, 2
+    p = params(n, W)
+    coords, acc = abi.alloc_state(p)
+    abi.init_walkers(p, coords, acc, fcc_start=True)
+    log = torch.full((W, n, 4), float("nan"), dtype=torch.float64, device="cuda")
+    abi.sweep(p, coords, acc, 0, 1, 0, 1, movelog=log)
+    torch.cuda.synchronize()
+    g = log.cpu().numpy()
+    xs = coords.cpu().numpy()
+    ag = abi.acc_to_numpy(acc)
+    o = _oracle_logs(osys(n), range(W), 1, 0, 1)
+    for w in range(W):
+        rec, a, x = o[w]
+        compare_fp64(g[w], rec, rows_form=False)
+        assert ag["n_acc"][w] == a.n_acc and ag["n_try"][w] == a.n_try == n
+        assert ag["n_samples"][w] == a.n_samples == 1
+        assert np.max(np.abs(xs[w] - x)) < 1e-9
+        assert ag["sum_e"][w] + ag["c_e"][w] == pytest.approx(a.sum_e + a.c_e, rel=1e-10)
+        assert ag["sum_vs"][w] + ag["c_vs"][w] == pytest.approx(a.sum_vs + a.c_vs, rel=1e-10)
+    assert 0.35 < g[:, :, 1].mean() < 0.7
+
+
+def test_spread_every_move_follows_the_oracle_fp32():
+    """N = 14000 in FP32 (168 KB of coordinates, two workgroups), one walker,
+    one sweep, move by move within the FP32 bounds."""
+    n = 14000
+    p = params(n, 1, abi.FP32)
+    assert abi.plan_launch(p)["slices"] == 2
+    coords, acc = abi.alloc_state(p)
+    abi.init_walkers(p, coords, acc, fcc_start=True)
+    log = torch.full((1, n, 4), float("nan"), dtype=torch.float64, device="cuda")
+    abi.sweep(p, coords, acc, 0, 1, movelog=log)
+    torch.cuda.synchronize()
+    s_ = osys(n, fp32=True)
+    o = _oracle_logs(s_, [0], 1, 0xFFFFFFFF, 0)
+    xl = _xi_logs(s_, 0, n, n)
+    end, _ = compare_fp32(log.cpu().numpy()[0], o[0][0], xl, False, min_moves=n // 4, L=s_.L)
+
+
+def test_spread_wait_that_gives_up_is_reported(monkeypatch):
+    """A zero poll limit (forced from the host): a workgroup that finds the
+    others not yet arrived gives up at once, the others give up in turn, and
+    the call reports HEVMC_EDEVICE; a normal call then runs."""
+    n, W = 8000, 2
+    p = params(n, W)
+    coords, acc = abi.alloc_state(p)
+    abi.init_walkers(p, coords, acc, fcc_start=True)
+    monkeypatch.setenv("HEVMC_SPREAD_SPIN_CAP", "0")
+    with pytest.raises(abi.HevmcError) as ei:
+        abi.sweep(p, coords, acc, 0, 1)
+    assert ei.value.code == -4 and "gave up" in str(ei.value)
+    monkeypatch.delenv("HEVMC_SPREAD_SPIN_CAP")
+    abi.init_walkers(p, coords, acc, fcc_start=True)
+    abi.sweep(p, coords, acc, 0, 1)
+    torch.cuda.synchronize()
+    a = abi.acc_to_numpy(acc)
+    assert np.all(np.isfinite(a["u_run"]))
