@@ -49,7 +49,8 @@ typedef enum {
     HEVMC_ENOMEM = -2,   /* device or host allocation failed                   */
     HEVMC_ENOFIT = -3,   /* walker does not fit in one workgroup's LDS         */
     HEVMC_EDEVICE = -4,  /* HIP runtime error (no device, launch failure, ...) */
-    HEVMC_ESTATE = -5    /* non-finite running state or accumulator detected   */
+    HEVMC_ESTATE = -5,   /* non-finite running state or accumulator detected   */
+    HEVMC_EBUSY = -6     /* the ensemble is in use by a call on another thread */
 } hevmc_status;
 
 typedef enum {
@@ -134,12 +135,13 @@ typedef struct {
  * LDS (FP64 beyond about 6800 atoms, FP32 beyond about 13600) is spread over
  * C workgroups of a cooperative launch, workgroup g holding atoms
  * [g S, g S + S): the cooperative kernel that Sec. 3 describes, over several
- * compute units.  Each micro-update's Eq. (7) sums are formed by the C
- * workgroups over their own atoms, published to a mailbox in device memory and
- * added in a fixed order by every workgroup after all C have arrived, so all
- * take the same Eq. (5) decision; the walker's coordinates in device memory are
- * the reference copy of positions.  Such walkers use the plain form (no rows;
- * a rows argument is ignored) with 256 threads per workgroup; their local
+ * compute units (C <= 14).  Each micro-update's Eq. (7) sums are formed by
+ * the C workgroups over their own atoms, published to a mailbox in device
+ * memory and added in a fixed order by every workgroup once all C are there,
+ * so all take the same Eq. (5) decision; the workgroup holding the next move's
+ * atom publishes its position the same way.  Such walkers use the plain form
+ * (no rows; a rows argument is ignored) with 512 threads per workgroup (256
+ * or 1024 if hevmc_params.threads asks for it); their local
  * energies run in a separate kernel, one workgroup per walker streaming the
  * coordinates through LDS.  hevmc_init_walkers, hevmc_sweep, hevmc_sweep_log,
  * hevmc_local_energy, hevmc_footprint, hevmc_plan_launch and the ensemble
@@ -318,9 +320,15 @@ hevmc_status hevmc_create(const hevmc_params *p, const double *init_xyz, void *s
 
 /* Create an ensemble on caller-owned device buffers (coords [W][3][N] of the
  * precision's type, already holding valid positions; acc [W]).  The buffers
- * must outlive the ensemble.  Initialises acc from coords; asynchronous. */
+ * must outlive the ensemble.  Initialises acc from coords; asynchronous.  When
+ * the plan uses row sums the ensemble allocates its own row buffer (8 N W
+ * bytes), which hevmc_destroy frees. */
 hevmc_status hevmc_create_on(const hevmc_params *p, void *dev_coords, hevmc_walker_acc *dev_acc,
                              void *stream, hevmc_ensemble **out);
+
+/* The calls on an ensemble below (run, sync, get_*, destroy) hold it while
+ * they run: a call on the same ensemble from another thread meanwhile returns
+ * HEVMC_EBUSY and does nothing. */
 
 /* Run n_sweeps more sweeps.  measure != 0 starts (or continues) measuring:
  * the first measured sweep fixes measure_start.  Asynchronous. */

@@ -22,7 +22,7 @@ VARIANT_ROWS = 2
 NO_MEASURE = 0xFFFFFFFF
 
 STATUS = {0: "HEVMC_OK", -1: "HEVMC_EINVAL", -2: "HEVMC_ENOMEM", -3: "HEVMC_ENOFIT",
-          -4: "HEVMC_EDEVICE", -5: "HEVMC_ESTATE"}
+          -4: "HEVMC_EDEVICE", -5: "HEVMC_ESTATE", -6: "HEVMC_EBUSY"}
 
 
 class HevmcError(RuntimeError):

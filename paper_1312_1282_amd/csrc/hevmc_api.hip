@@ -180,17 +180,20 @@ hevmc_status plan_spread(const hevmc_params *p, void *stream, Launch &L, const D
 {
     const bool fp32 = p->precision == HEVMC_FP32;
     const size_t tsz = fp32 ? sizeof(float) : sizeof(double);
-    const int threads = 256;
+    // 512 threads (two waves per SIMD) unless the caller asks for 256 or 1024
+    const int threads = (p->threads == 256 || p->threads == 1024) ? p->threads : 512;
     const size_t stat = static_lds(threads);
     const size_t max_dyn = d.lds_per_block > stat ? d.lds_per_block - stat : 0;
+    // at most 14 slices: one wave polls a move's 4C + 6 mailbox words, one per lane
+    const int c_max = std::min(14, d.cus);
     int C = 2;
     int S = (p->n + C - 1) / C;
-    while ((size_t)3 * (size_t)S * tsz > max_dyn && C < d.cus) {
+    while ((size_t)3 * (size_t)S * tsz > max_dyn && C < c_max) {
         ++C;
         S = (p->n + C - 1) / C;
     }
     if ((size_t)3 * (size_t)S * tsz > max_dyn)
-        return fail(HEVMC_ENOFIT, "walker of %d atoms does not fit in %d workgroups' LDS", p->n, d.cus);
+        return fail(HEVMC_ENOFIT, "walker of %d atoms does not fit in %d workgroups' LDS", p->n, c_max);
     make_kparams(p, L.k);
     L.k.sorted = 0;
     L.p.n_walkers_grid = p->n_walkers;
@@ -525,15 +528,14 @@ static hevmc_status sweep_spread(const Launch &L, const hevmc_params *p, void *c
     if (max_group < 1)
         return fail(HEVMC_ENOFIT, "a walker of %d slices does not fit on the chip at once", C);
     const int W = p->n_walkers, G = std::min(W, max_group);
-    const size_t mail_bytes = (size_t)G * 4 * (size_t)C * sizeof(double);
-    const size_t bytes = mail_bytes + (size_t)G * sizeof(uint32_t) + 64;
+    const size_t mail_bytes = (size_t)G * 2 * (size_t)(4 * C + 8) * sizeof(uint64_t);
+    const size_t bytes = mail_bytes + 64;
     void *ws = nullptr;
     if ((st = spread_workspace(bytes, &ws)) != HEVMC_OK)
         return st;
     CoopArgs c;
-    c.mail = static_cast<double *>(ws);
-    c.arrive = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + mail_bytes);
-    c.status = c.arrive + G;
+    c.mail = static_cast<uint64_t *>(ws);
+    c.status = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + mail_bytes);
     c.spin_cap = spread_spin_cap();
     c.C = C;
     c.S = L.slice_atoms;
@@ -573,9 +575,10 @@ static hevmc_status sweep_spread(const Launch &L, const hevmc_params *p, void *c
                 }
             }
             c.log_base = (int64_t)(t - sweep0) * p->n;
-            e = hipMemsetAsync(c.arrive, 0, (size_t)g * sizeof(uint32_t), L.stream);
+            // sequence numbers restart with each launch
+            e = hipMemsetAsync(c.mail, 0, (size_t)g * 2 * (size_t)(4 * C + 8) * sizeof(uint64_t), L.stream);
             if (e != hipSuccess)
-                return hip_fail(e, "arrival counter reset");
+                return hip_fail(e, "mailbox reset");
             if ((st = launched(launch_sweep_coop(Lg, c, cg, ag, (uint32_t)t, (int32_t)(te - t + 1), mstart, g),
                                "cooperative sweep launch")) != HEVMC_OK)
                 return st;
@@ -804,11 +807,33 @@ struct hevmc_ensemble {
     hipStream_t stream;
     void *coords;
     hevmc_walker_acc *acc;
-    double *rows;       // row sums kept between launches (owned), or null
-    bool owns;
+    double *rows;       // row sums kept between launches (always owned), or null
+    bool owns;          // coords and acc allocated by the library
     uint32_t sweep;
     uint32_t mstart;
+    std::atomic<bool> busy{false};   // a call on the ensemble is running
 };
+
+namespace {
+
+// Holds an ensemble for the duration of one call; a second call on another
+// thread meanwhile gets HEVMC_EBUSY instead of racing on its state.
+struct EnsembleHold {
+    hevmc_ensemble *e;
+    bool held;
+    explicit EnsembleHold(hevmc_ensemble *e_) : e(e_), held(e_ && !e_->busy.exchange(true)) {}
+    ~EnsembleHold()
+    {
+        if (held)
+            e->busy.store(false);
+    }
+    hevmc_status refused() const
+    {
+        return fail(HEVMC_EBUSY, "the ensemble is in use by a call on another thread");
+    }
+};
+
+}  // namespace
 
 namespace {
 
@@ -918,9 +943,20 @@ extern "C" hevmc_status hevmc_create_on(const hevmc_params *p, void *dev_coords,
     e->owns = false;
     e->sweep = 0;
     e->mstart = 0xFFFFFFFFu;
-    st = hevmc_init_walkers(p, dev_coords, dev_acc, nullptr, 0, stream);
+    // the row sums of the row-sum sweep persist between runs in a buffer of
+    // the ensemble's own (8 N W bytes), as for hevmc_create
+    if (L.rows || L.rreg) {
+        const size_t rbytes = sizeof(double) * (size_t)p->n * (size_t)p->n_walkers;
+        if (hipMalloc((void **)&e->rows, rbytes) != hipSuccess) {
+            delete e;
+            return fail(HEVMC_ENOMEM, "hipMalloc of %zu B for row sums failed", rbytes);
+        }
+    }
+    st = hevmc_init_walkers(p, dev_coords, dev_acc, e->rows, 0, stream);
     if (st != HEVMC_OK) {
-        delete e;
+        std::string msg = g_err;
+        hevmc_destroy(e);
+        g_err = msg;
         return st;
     }
     *out = e;
@@ -931,6 +967,9 @@ extern "C" hevmc_status hevmc_run(hevmc_ensemble *e, int32_t n_sweeps, int32_t e
 {
     if (!e)
         return fail(HEVMC_EINVAL, "ensemble is NULL");
+    EnsembleHold hold(e);
+    if (!hold.held)
+        return hold.refused();
     if (n_sweeps < 0)
         return fail(HEVMC_EINVAL, "n_sweeps = %d must be >= 0", n_sweeps);
     if (measure && e->mstart == 0xFFFFFFFFu)
@@ -943,10 +982,10 @@ extern "C" hevmc_status hevmc_run(hevmc_ensemble *e, int32_t n_sweeps, int32_t e
     return st;
 }
 
-extern "C" hevmc_status hevmc_get_acc(hevmc_ensemble *e, hevmc_walker_acc *host_out)
+namespace {
+
+hevmc_status get_acc(hevmc_ensemble *e, hevmc_walker_acc *host_out)
 {
-    if (!e || !host_out)
-        return fail(HEVMC_EINVAL, "ensemble and host_out must not be NULL");
     hipError_t he = hipMemcpyAsync(host_out, e->acc, sizeof(hevmc_walker_acc) * (size_t)e->p.n_walkers,
                                    hipMemcpyDeviceToHost, e->stream);
     if (he == hipSuccess)
@@ -963,18 +1002,36 @@ extern "C" hevmc_status hevmc_get_acc(hevmc_ensemble *e, hevmc_walker_acc *host_
     return HEVMC_OK;
 }
 
+}  // namespace
+
+extern "C" hevmc_status hevmc_get_acc(hevmc_ensemble *e, hevmc_walker_acc *host_out)
+{
+    if (!e || !host_out)
+        return fail(HEVMC_EINVAL, "ensemble and host_out must not be NULL");
+    EnsembleHold hold(e);
+    if (!hold.held)
+        return hold.refused();
+    return get_acc(e, host_out);
+}
+
 extern "C" hevmc_status hevmc_sync(hevmc_ensemble *e)
 {
     if (!e)
         return fail(HEVMC_EINVAL, "ensemble is NULL");
+    EnsembleHold hold(e);
+    if (!hold.held)
+        return hold.refused();
     std::vector<hevmc_walker_acc> tmp((size_t)e->p.n_walkers);
-    return hevmc_get_acc(e, tmp.data());
+    return get_acc(e, tmp.data());
 }
 
 extern "C" hevmc_status hevmc_get_coords(hevmc_ensemble *e, double *host_out)
 {
     if (!e || !host_out)
         return fail(HEVMC_EINVAL, "ensemble and host_out must not be NULL");
+    EnsembleHold hold(e);
+    if (!hold.held)
+        return hold.refused();
     const size_t count = (size_t)e->p.n_walkers * 3 * (size_t)e->p.n;
     hipError_t he;
     if (e->p.precision == HEVMC_FP32) {
@@ -996,6 +1053,9 @@ extern "C" hevmc_status hevmc_get_sweep(hevmc_ensemble *e, uint32_t *sweep_out)
 {
     if (!e || !sweep_out)
         return fail(HEVMC_EINVAL, "ensemble and sweep_out must not be NULL");
+    EnsembleHold hold(e);
+    if (!hold.held)
+        return hold.refused();
     *sweep_out = e->sweep;
     return HEVMC_OK;
 }
@@ -1004,15 +1064,19 @@ extern "C" hevmc_status hevmc_destroy(hevmc_ensemble *e)
 {
     if (!e)
         return HEVMC_OK;
+    if (e->busy.exchange(true))
+        return fail(HEVMC_EBUSY, "the ensemble is in use by a call on another thread; not destroyed");
     hevmc_status st = HEVMC_OK;
-    if (e->owns) {
+    if (e->owns || e->rows) {
         hipError_t he = hipStreamSynchronize(e->stream);
         if (he != hipSuccess)
             st = hip_fail(he, "synchronise before free");
+    }
+    if (e->owns) {
         (void)hipFree(e->coords);
         (void)hipFree(e->acc);
-        (void)hipFree(e->rows);
     }
+    (void)hipFree(e->rows);
     delete e;
     return st;
 }

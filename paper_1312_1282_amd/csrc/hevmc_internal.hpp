@@ -76,9 +76,11 @@ struct BatchArgs {
 // Eq. (7) sums of its C slices for the two parities of the micro-update
 // counter ([W][2][C][2] doubles) and an arrival counter ([W], zero at launch);
 // status becomes nonzero if a wait gave up after spin_cap polls.
+// The cooperative sweep's exchange: per walker two rows of 4C + 8 mailbox
+// words (zeroed before each launch), and a status word set by a workgroup
+// whose wait gave up.
 struct CoopArgs {
-    double *mail;
-    uint32_t *arrive;
+    uint64_t *mail;
     uint32_t *status;
     uint32_t spin_cap;
     int32_t C;          // workgroups (slices) per walker

@@ -104,7 +104,9 @@ __device__ __forceinline__ bool walker_any(bool pred, double *buf)
     } else {
         double f[1] = {pred ? 1.0 : 0.0};
         block_sum<NT, 1>(f, buf);
-        return f[0] > 0.0;
+        // decided here as one wave-uniform word, so that the partial sums are
+        // not kept alive until the flag's use at the end of a launch
+        return __builtin_amdgcn_readfirstlane(f[0] > 0.0 ? 1 : 0) != 0;
     }
 }
 
@@ -1534,15 +1536,14 @@ hipError_t launch_move_delta(const Launch &L, const void *coords, const int32_t 
 // the walker in its LDS.  Every micro-update is decided by all C workgroups
 // together: each forms the Eq. (7) sums over its own atoms (the plain form:
 // u and V at the old and the new position), publishes them to a mailbox in
-// device memory, and waits until all C have arrived; every workgroup then
+// device memory, and waits until all C have published; every workgroup then
 // adds the C partial sums in the same order and takes the same decision.
-// The walker's coordinates in device memory are the reference copy: the
-// owner of an accepted atom writes its new position there, and the others
-// read old positions of atoms outside their slice from it.  Every wait is
-// bounded: after spin_cap polls the workgroup gives up, records the timeout
-// in *status and leaves; the others then time out in turn, so the grid
-// always drains.  Local energies of such walkers come from a separate kernel
-// with one workgroup per walker that streams the partners through LDS tiles.
+// The workgroup holding the next move's atom publishes its position in the
+// same way.  Every wait is bounded: after spin_cap polls the workgroup gives
+// up, records the timeout in *status and leaves; the others then time out in
+// turn, so the grid always drains.  Local energies of such walkers come from
+// a separate kernel with one workgroup per walker that streams the partners
+// through LDS tiles.
 
 // Local energy terms (or just the running totals U, V) of walker blockIdx.x,
 // with the coordinates read from device memory in tiles of `tile` atoms.
@@ -1644,28 +1645,99 @@ __global__ void k_fcc_global(KParams p, T *__restrict__ coords, int n_walkers, i
     fcc_site<T>(p, p.wid_base + (uint32_t)w, i, nc, a_lat, &g[i], &g[n + i], &g[2 * n + i]);
 }
 
+// Mailbox words of the cooperative sweep: 32 bits of sequence number (the
+// launch's micro-update count plus one) over 32 bits of payload.  A word is
+// read with one relaxed device-scope atomic load and is valid when its
+// sequence matches, so no fence orders it against any other word.
+__device__ __forceinline__ void mail_put(uint64_t *w, uint32_t seq, uint32_t payload)
+{
+    __hip_atomic_store(w, ((uint64_t)seq << 32) | payload, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Payload word q (0 or 1: high or low half) of a double.
+__device__ __forceinline__ uint32_t half_of(double v, int q)
+{
+    return (uint32_t)(q == 0 ? __double2hiint(v) : __double2loint(v));
+}
+
+// Publishes an atom's position in PW words (FP64: high and low halves of x,
+// y, z; FP32: the bits of x, y, z).
+__device__ __forceinline__ void put_position(uint64_t *w, uint32_t seq, double x, double y, double z)
+{
+    mail_put(w + 0, seq, half_of(x, 0));
+    mail_put(w + 1, seq, half_of(x, 1));
+    mail_put(w + 2, seq, half_of(y, 0));
+    mail_put(w + 3, seq, half_of(y, 1));
+    mail_put(w + 4, seq, half_of(z, 0));
+    mail_put(w + 5, seq, half_of(z, 1));
+}
+__device__ __forceinline__ void put_position(uint64_t *w, uint32_t seq, float x, float y, float z)
+{
+    mail_put(w + 0, seq, __float_as_uint(x));
+    mail_put(w + 1, seq, __float_as_uint(y));
+    mail_put(w + 2, seq, __float_as_uint(z));
+}
+
+// The position published in words lo .. lo + PW - 1 held by the lanes of
+// the same index (wave-uniform result).
+__device__ __forceinline__ void get_position(uint32_t word, int lo, double &x, double &y, double &z)
+{
+    x = __hiloint2double(readlane_i((int)word, lo), readlane_i((int)word, lo + 1));
+    y = __hiloint2double(readlane_i((int)word, lo + 2), readlane_i((int)word, lo + 3));
+    z = __hiloint2double(readlane_i((int)word, lo + 4), readlane_i((int)word, lo + 5));
+}
+__device__ __forceinline__ void get_position(uint32_t word, int lo, float &x, float &y, float &z)
+{
+    x = __uint_as_float((uint32_t)readlane_i((int)word, lo));
+    y = __uint_as_float((uint32_t)readlane_i((int)word, lo + 1));
+    z = __uint_as_float((uint32_t)readlane_i((int)word, lo + 2));
+}
+
 // The cooperative sweep of spread walkers: workgroup blockIdx.x serves slice
 // g = blockIdx.x % c.C of walker blockIdx.x / c.C.  Sweeps t = sweep0 ..
 // sweep0 + nsw - 1, the plain form of Eq. (7) (u and V at both positions),
 // no local-energy samples (the caller runs them between launches); measured
 // sweeps count moves and add v_run to sum_vs.  Movelog as in k_sweep.
+//
+// Per micro-update mv (parity par = mv & 1 picks one of two mailbox rows of
+// the walker, 4C + 8 words each):
+//  * every workgroup knows the moved atom's old position (see below) and
+//    forms the trial position;
+//  * the lane holding the next micro-update's atom in its slice (if that
+//    atom is another one) publishes the atom's position in words 4C ..;
+//  * each workgroup forms its partial Eq. (7) sums over its slice and lanes
+//    0..3 of wave 0 publish them in words 4g .. 4g + 3 (FP64 halves);
+//  * wave 0 polls all words it needs until every one carries this move's
+//    sequence (bounded by spin_cap polls), adds the C partials in slice
+//    order and hands the totals and the next old position to the other
+//    waves through LDS; every workgroup takes the same decision.
+// A row is written again two moves later, only after its writer has seen
+// every workgroup's words of the move in between, which each wrote after
+// reading this row.  The next move's old position is the published one, or,
+// for the same atom again, the trial position if accepted and the old one if
+// not; the first move of a launch reads it from device memory, which the
+// launch writes only at its end (each workgroup its slice).
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_sweep_coop(KParams p, CoopArgs c, T *__restrict__ coords,
                                                    hevmc_walker_acc *__restrict__ accs, uint32_t sweep0,
                                                    int32_t nsw, uint32_t mstart)
 {
     constexpr int NW = NT / 64;
+    constexpr int PW = sizeof(T) == 8 ? 6 : 3;   // words of a published position
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[NW][2];
-    __shared__ double tot[2];
+    __shared__ double tot[5];   // dU, dV, the next old position
     __shared__ int fail_flag;
     const int w = (int)(blockIdx.x / (uint32_t)c.C), g = (int)(blockIdx.x % (uint32_t)c.C);
     const int n = p.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int C = c.C;
     const int i0 = g * c.S, ns = min(c.S, n - i0);   // this workgroup's atoms [i0, i0 + ns)
     T *gx = coords + (size_t)w * 3 * (size_t)n;
     T *gy = gx + n, *gz = gy + n;
     T *sx = reinterpret_cast<T *>(smem_raw);
     T *sy = sx + c.S, *sz = sy + c.S;
+    // thread q % NT owns slice atom q: it loads it, writes its moves and
+    // stores it back, so its LDS entry needs no barrier
     for (int i = tid; i < ns; i += NT) {
         sx[i] = gx[i0 + i];
         sy[i] = gy[i0 + i];
@@ -1678,45 +1750,48 @@ __global__ __launch_bounds__(NT) void k_sweep_coop(KParams p, CoopArgs c, T *__r
     double u_run = accp->u_run, v_run = accp->v_run;
     int64_t n_acc = 0, n_try = 0, n_swm = 0;
     const uint32_t wid = p.wid_base + (uint32_t)w;
-    double *mail = c.mail + (size_t)w * 4 * (size_t)c.C;
-    uint32_t *arrive = c.arrive + w;
+    const int row_words = 4 * C + 8;
+    uint64_t *mail = c.mail + (size_t)w * 2 * (size_t)row_words;
     double *mlw = (p.movelog && w < p.log_walkers && g == 0) ? p.movelog + (size_t)w * (size_t)p.log_cap * 4
                                                              : nullptr;
-    uint32_t mv = 0;          // micro-updates of this launch
-    int last_s = -1;          // atom accepted in the previous micro-update
-    T lx = 0, ly = 0, lz = 0; // its new position
+    uint32_t mv = 0;   // micro-updates of this launch
     bool failed = false;
+    // this batch's moves (lane l: micro-step k0 + l) and the next batch's
+    int bs, nbs = 0;
+    double bxi, bdx, bdy, bdz, nbxi = 0.5, nbdx = 0.0, nbdy = 0.0, nbdz = 0.0;
+    draw_move(p, (uint32_t)lane, sweep0, wid, bs, bxi, bdx, bdy, bdz);
+    double blx = log(bxi);
+    T ox = 0, oy = 0, oz = 0;   // old position of the current micro-update's atom
+    {
+        const int s0 = readlane_i(bs, 0);
+        ox = gx[s0];
+        oy = gy[s0];
+        oz = gz[s0];
+    }
     for (int it = 0; it < nsw && !failed; ++it) {
         const uint32_t t = sweep0 + (uint32_t)it;
         const bool measured = t >= mstart;
         for (int k0 = 0; k0 < n && !failed; k0 += 64) {
-            int bs;
-            double bxi, bdx, bdy, bdz;
-            draw_move(p, (uint32_t)(k0 + lane), t, wid, bs, bxi, bdx, bdy, bdz);
-            const double blx = log(bxi);
-            // old and trial positions of the batch from the reference copy
-            // (current for every atom but the one accepted just before: its
-            // micro-update's barrier-free write may not be seen yet)
-            const T bnx = trial_coord<T>((double)gx[bs] + bdx, p);
-            const T bny = trial_coord<T>((double)gy[bs] + bdy, p);
-            const T bnz = trial_coord<T>((double)gz[bs] + bdz, p);
-            uint64_t stale = last_s >= 0 ? __builtin_amdgcn_ballot_w64(bs == last_s) : 0ull;
+            // the batch after this one (in the next sweep after the last batch)
+            const bool next_in_sweep = k0 + 64 < n;
+            const bool has_next = next_in_sweep || it + 1 < nsw;
+            if (has_next)
+                draw_move(p, (uint32_t)((next_in_sweep ? k0 + 64 : 0) + lane), next_in_sweep ? t : t + 1u, wid,
+                          nbs, nbxi, nbdx, nbdy, nbdz);
             const int kend = min(64, n - k0);
             for (int j = 0; j < kend; ++j) {
                 const int s = readlane_i(bs, j);
                 const double lxi = lane_value(blx, j);
-                T ox, oy, oz, nx, ny, nz;
-                if (s == last_s) {
-                    ox = lx; oy = ly; oz = lz;
-                } else {
-                    ox = gx[s]; oy = gy[s]; oz = gz[s];
-                }
-                if ((stale >> j) & 1ull) {
-                    nx = trial_coord<T>((double)ox + lane_value(bdx, j), p);
-                    ny = trial_coord<T>((double)oy + lane_value(bdy, j), p);
-                    nz = trial_coord<T>((double)oz + lane_value(bdz, j), p);
-                } else {
-                    nx = lane_value(bnx, j); ny = lane_value(bny, j); nz = lane_value(bnz, j);
+                const int s_next = j + 1 < kend ? readlane_i(bs, j + 1) : has_next ? readlane_i(nbs, 0) : -1;
+                const bool pub = s_next >= 0 && s_next != s;
+                const uint32_t par = mv & 1u, seq = mv + 1u;
+                uint64_t *row = mail + (size_t)par * (size_t)row_words;
+                const T nx = trial_coord<T>((double)ox + lane_value(bdx, j), p);
+                const T ny = trial_coord<T>((double)oy + lane_value(bdy, j), p);
+                const T nz = trial_coord<T>((double)oz + lane_value(bdz, j), p);
+                if (pub && s_next >= i0 && s_next < i0 + ns && tid == (s_next - i0) % NT) {
+                    const int q = s_next - i0;
+                    put_position(row + 4 * C, seq, sx[q], sy[q], sz[q]);
                 }
                 // this workgroup's part of the Eq. (7) sums
                 double du = 0.0, dv = 0.0;
@@ -1738,37 +1813,50 @@ __global__ __launch_bounds__(NT) void k_sweep_coop(KParams p, CoopArgs c, T *__r
                     red[wave][1] = dv;
                 }
                 __syncthreads();
-                if (tid == 0) {
+                if (wave == 0) {
                     double pu = 0.0, pv = 0.0;
                     for (int q = 0; q < NW; ++q) {
                         pu += red[q][0];
                         pv += red[q][1];
                     }
-                    double *slot = mail + ((size_t)(mv & 1u) * c.C + g) * 2;
-                    slot[0] = pu;
-                    slot[1] = pv;
-                    __threadfence();
-                    atomicAdd(arrive, 1u);
-                    const uint32_t target = (mv + 1u) * (uint32_t)c.C;
+                    if (lane < 4)
+                        mail_put(row + 4 * g + lane, seq, half_of(lane < 2 ? pu : pv, lane & 1));
+                    // every word of this move: the C partials and the published position
+                    const int nw = 4 * C + (pub ? PW : 0);
+                    uint64_t word = 0;
+                    bool have = lane >= nw;
                     uint32_t spins = 0;
                     int f = 0;
-                    while (__hip_atomic_load(arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                    while (true) {
+                        if (!have) {
+                            word = __hip_atomic_load(row + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            have = (uint32_t)(word >> 32) == seq;
+                        }
+                        if (__builtin_amdgcn_ballot_w64(!have) == 0ull)
+                            break;
                         if (++spins > c.spin_cap) {
                             f = 1;
                             break;
                         }
                         __builtin_amdgcn_s_sleep(1);
                     }
-                    __threadfence();
+                    const uint32_t pay = (uint32_t)word;
                     double DU = 0.0, DV = 0.0;
-                    const double *row = mail + (size_t)(mv & 1u) * c.C * 2;
-                    for (int q = 0; q < c.C; ++q) {
-                        DU += __hip_atomic_load(row + 2 * q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        DV += __hip_atomic_load(row + 2 * q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    for (int q = 0; q < C; ++q) {
+                        DU += __hiloint2double(readlane_i((int)pay, 4 * q), readlane_i((int)pay, 4 * q + 1));
+                        DV += __hiloint2double(readlane_i((int)pay, 4 * q + 2), readlane_i((int)pay, 4 * q + 3));
                     }
-                    tot[0] = DU;
-                    tot[1] = DV;
-                    fail_flag = f;
+                    T px = 0, py = 0, pz = 0;
+                    if (pub)
+                        get_position(pay, 4 * C, px, py, pz);
+                    if (lane == 0) {
+                        tot[0] = DU;
+                        tot[1] = DV;
+                        tot[2] = (double)px;
+                        tot[3] = (double)py;
+                        tot[4] = (double)pz;
+                        fail_flag = f;
+                    }
                 }
                 __syncthreads();
                 if (fail_flag) {
@@ -1794,16 +1882,32 @@ __global__ __launch_bounds__(NT) void k_sweep_coop(KParams p, CoopArgs c, T *__r
                     u_run += DU;
                     v_run += DV;
                     if (s >= i0 && s < i0 + ns && tid == (s - i0) % NT) {
-                        sx[s - i0] = nx; sy[s - i0] = ny; sz[s - i0] = nz;
-                        gx[s] = nx; gy[s] = ny; gz[s] = nz;
+                        sx[s - i0] = nx;
+                        sy[s - i0] = ny;
+                        sz[s - i0] = nz;
                     }
-                    const uint64_t later = j >= 63 ? 0ull : (~0ull << (j + 1));
-                    stale |= __builtin_amdgcn_ballot_w64(bs == s) & later;
-                    last_s = s;
-                    lx = nx; ly = ny; lz = nz;
-                } else {
-                    last_s = -1;
                 }
+                // the next micro-update's old position
+                if (!pub) {
+                    if (accept) {
+                        ox = nx;
+                        oy = ny;
+                        oz = nz;
+                    }
+                } else {
+                    ox = (T)tot[2];
+                    oy = (T)tot[3];
+                    oz = (T)tot[4];
+                }
+                // tot is written again only after the next move's first barrier
+            }
+            if (has_next) {
+                bs = nbs;
+                bxi = nbxi;
+                bdx = nbdx;
+                bdy = nbdy;
+                bdz = nbdz;
+                blx = log(bxi);
             }
         }
         if (measured && !failed) {
@@ -1817,6 +1921,11 @@ __global__ __launch_bounds__(NT) void k_sweep_coop(KParams p, CoopArgs c, T *__r
             atomicOr(c.status, 1u);
         return;
     }
+    for (int i = tid; i < ns; i += NT) {
+        gx[i0 + i] = sx[i];
+        gy[i0 + i] = sy[i];
+        gz[i0 + i] = sz[i];
+    }
     if (g == 0 && tid == 0) {
         accp->u_run = u_run;
         accp->v_run = v_run;
@@ -1826,11 +1935,15 @@ __global__ __launch_bounds__(NT) void k_sweep_coop(KParams p, CoopArgs c, T *__r
     }
 }
 
+// workgroup sizes of the cooperative sweep (the plan picks one of them)
+template <int NT>
+constexpr bool kCoopThreads = NT == 256 || NT == 512 || NT == 1024;
+
 template <typename T, int NT>
 static hipError_t launch_coop_t(const Launch &L, const CoopArgs &c, void *coords, hevmc_walker_acc *acc,
                                 uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t walkers)
 {
-    if constexpr (NT != 256) {
+    if constexpr (!kCoopThreads<NT>) {
         return hipErrorInvalidValue;
     } else {
         auto kern = k_sweep_coop<T, NT>;
@@ -1849,7 +1962,7 @@ static hipError_t launch_coop_t(const Launch &L, const CoopArgs &c, void *coords
 template <typename T, int NT>
 static hipError_t coop_capacity_t(const Launch &L, int *blocks_per_cu)
 {
-    if constexpr (NT != 256) {
+    if constexpr (!kCoopThreads<NT>) {
         return hipErrorInvalidValue;
     } else {
         auto kern = k_sweep_coop<T, NT>;
@@ -1895,8 +2008,11 @@ hipError_t coop_blocks_per_cu(const Launch &L, int *blocks_per_cu)
     HEVMC_DISPATCH(coop_capacity_t, blocks_per_cu);
 }
 
-hipError_t launch_energy_global(const Launch &L, const void *coords, hevmc_walker_acc *acc, double *out, int mode)
+hipError_t launch_energy_global(const Launch &Ls, const void *coords, hevmc_walker_acc *acc, double *out, int mode)
 {
+    // 256 threads whatever the sweep's workgroup size (no spills at this size)
+    Launch L = Ls;
+    L.threads = 256;
     const int tile = L.fp32 ? 4096 : 2048;
     HEVMC_DISPATCH(launch_energy_global_t, coords, acc, out, mode, tile);
 }

@@ -470,6 +470,58 @@ def test_non_finite_state_is_reported(threads):
     assert abi.lib().hevmc_destroy(h) == 0
 
 
+def test_create_on_keeps_its_row_sums_between_runs():
+    """An ensemble on caller-owned buffers keeps the row sums of the row-sum
+    sweep in a buffer of its own between runs, as hevmc_create does: two runs
+    give the bits of the stateless calls with one rows buffer carried through
+    (rebuilding the rows from scratch would change the last bits)."""
+    import ctypes as C
+    n, W = 256, 4
+    p = gparams(n, W, threads=128)
+    assert abi.plan_uses_rows(p)
+    s_ = osys(n)
+    xs = np.stack([grid_config(n, s_.L, seed=w) for w in range(W)])
+    c1, a1 = torch.from_numpy(xs).cuda(), torch.zeros((W, abi.ACC_BYTES), dtype=torch.uint8, device="cuda")
+    rows = abi.alloc_rows(p)
+    abi.init_walkers(p, c1, a1, fcc_start=False, rows=rows)
+    abi.sweep(p, c1, a1, 0, 3, abi.NO_MEASURE, 0, rows=rows)
+    abi.sweep(p, c1, a1, 3, 4, 3, 2, rows=rows)
+    c2, a2 = torch.from_numpy(xs).cuda(), torch.zeros((W, abi.ACC_BYTES), dtype=torch.uint8, device="cuda")
+    h = C.c_void_p()
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert abi.lib().hevmc_create_on(C.byref(p), C.c_void_p(c2.data_ptr()), C.c_void_p(a2.data_ptr()), st,
+                                     C.byref(h)) == 0
+    assert abi.lib().hevmc_run(h, 3, 0, 0) == 0
+    assert abi.lib().hevmc_run(h, 4, 2, 1) == 0
+    assert abi.lib().hevmc_sync(h) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(c1, c2) and torch.equal(a1, a2)
+    assert abi.lib().hevmc_destroy(h) == 0
+
+
+def test_a_second_thread_on_a_busy_ensemble_gets_ebusy():
+    """While one thread waits in hevmc_sync for a long run, a call on the same
+    ensemble from another thread returns HEVMC_EBUSY and does nothing; once the
+    first call returns, the ensemble answers again."""
+    import ctypes as C
+    import threading
+    import time
+    wl = configs.C2_N2048_FP64
+    e = abi.Ensemble(abi.params_for(wl))
+    e.run(300)
+    res = {}
+    th = threading.Thread(target=lambda: res.setdefault("sync", abi.lib().hevmc_sync(e._h)))
+    th.start()
+    time.sleep(0.3)
+    s = C.c_uint32()
+    busy = abi.lib().hevmc_get_sweep(e._h, C.byref(s))
+    th.join()
+    assert busy == -6 and b"in use" in abi.lib().hevmc_last_error()
+    assert res["sync"] == 0
+    assert e.sweep_index() == 300
+    e.close()
+
+
 @pytest.mark.parametrize("wl,threads,variant,spatial", [
     (configs.C2_N2048_FP64, 256, abi.VARIANT_ROWS, 1),
     (configs.C3_N2048_FP32, 256, abi.VARIANT_ROWS, 1),

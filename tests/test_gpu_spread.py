@@ -30,8 +30,9 @@ B = configs.C1_SMALL_FP64.b
 STEP = configs.C1_SMALL_FP64.step_sigma
 
 
-def params(n, W, precision=abi.FP64, seed=17):
-    return abi.make_params(n, W, precision=precision, density=RHO, b=B, step_sigma=STEP, seed=seed)
+def params(n, W, precision=abi.FP64, seed=17, threads=0):
+    return abi.make_params(n, W, precision=precision, density=RHO, b=B, step_sigma=STEP, seed=seed,
+                           threads=threads)
 
 
 def osys(n, seed=17, fp32=False):
@@ -42,8 +43,11 @@ def osys(n, seed=17, fp32=False):
 def test_spread_plans():
     p = params(8000, 2)
     plan = abi.plan_launch(p)
-    assert (plan["slices"], plan["threads"], plan["variant"], plan["spatial_order"]) == (2, 256, abi.VARIANT_PLAIN, 0)
+    assert (plan["slices"], plan["threads"], plan["variant"], plan["spatial_order"]) == (2, 512, abi.VARIANT_PLAIN, 0)
     assert plan["lds_per_group"] >= 3 * 4000 * 8 and plan["lds_per_group"] <= 160 * 1024
+    for t in (256, 1024):
+        assert abi.plan_launch(params(8000, 2, threads=t))["threads"] == t
+    assert abi.plan_launch(params(40960, 1, abi.FP32))["slices"] == 4
     assert abi.plan_launch(params(14000, 1, abi.FP32))["slices"] == 2
     assert abi.plan_launch(params(2048, 1))["slices"] == 1
     assert abi.plan_launch(params(13000, 1, abi.FP32))["slices"] == 1   # rows in registers, one workgroup
@@ -88,11 +92,13 @@ def _oracle_logs(s_, walkers, n_sweeps, measure_start, m):
     return res
 
 
-def test_spread_every_move_follows_the_oracle_fp64():
+@pytest.mark.parametrize("threads", [0, 256, 1024])
+def test_spread_every_move_follows_the_oracle_fp64(threads):
     """N = 8000 in FP64 (192 KB of coordinates, two workgroups), two walkers,
-    one measured sweep with the local-energy sample that ends it."""
+    one measured sweep with the local-energy sample that ends it; workgroups
+    of the library's size (512 threads), of 256 and of 1024."""
     n, W = 8000, 2
-    p = params(n, W)
+    p = params(n, W, threads=threads)
     coords, acc = abi.alloc_state(p)
     abi.init_walkers(p, coords, acc, fcc_start=True)
     log = torch.full((W, n, 4), float("nan"), dtype=torch.float64, device="cuda")
