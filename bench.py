@@ -88,10 +88,12 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(workload):
-    """HBM bytes per sweep launch from the calibrated FETCH_SIZE + WRITE_SIZE
-    counters recorded in profiles/traffic.txt, if they were taken on the
-    kernel sources as they are now; else None."""
+def recorded_counters(workload):
+    """Per-launch figures of the sweep kernel recorded in profiles/traffic.txt
+    from rocprofv3 counters, if they were taken on the kernel sources as they
+    are now: {"traffic": HBM bytes (calibrated FETCH_SIZE + WRITE_SIZE),
+    "executed_flop": executed vector FLOPs (the SQ_INSTS_VALU_FLOPS_* counters
+    x 64 lanes), or None where not recorded}; else None."""
     import glob
     import hashlib
 
@@ -99,15 +101,17 @@ def measured_traffic(workload):
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1312_1282_amd", "csrc", "*"))):
+    csrc = os.path.join(ROOT, "paper_1312_1282_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
         with open(f, "rb") as fh:
             h.update(fh.read())
     digest = h.hexdigest()
     with open(path) as fh:
         for line in fh:
             parts = line.split()
-            if len(parts) == 3 and not line.startswith("#") and parts[0] == workload and parts[1] == digest:
-                return int(parts[2])
+            if len(parts) >= 3 and not line.startswith("#") and parts[0] == workload and parts[1] == digest:
+                return {"traffic": int(parts[2]),
+                        "executed_flop": int(parts[3]) if len(parts) > 3 else None}
     return None
 
 
@@ -683,6 +687,10 @@ def main():
     avg_s = float(launch_ms.mean()) * 1e-3
     achieved = flop_launch / avg_s / 1e12
 
+    rec = recorded_counters(wl.name) or {"traffic": None, "executed_flop": None}
+    executed = rec["executed_flop"] / avg_s / 1e12 if rec["executed_flop"] else None
+    spread = plan["slices"] > 1
+
     a = abi.acc_to_numpy(acc)
     ns = np.maximum(a["n_samples"], 1)
     e_w = (a["sum_e"] + a["c_e"]) / ns / wl.n
@@ -719,6 +727,7 @@ def main():
             "variant": "rows" if rows_variant else "plain",
             "spatial_order": bool(plan["spatial_order"]),
             "walkers_per_cu": plan["walkers_per_cu"],
+            "workgroups_per_walker": plan["slices"],
         },
         "roofline": {
             "bound": "alu",
@@ -726,9 +735,14 @@ def main():
             "peak": PEAK[dtype],
             "unit": "TFLOP/s",
             "frac": achieved / PEAK[dtype],
-            "traffic": measured_traffic(wl.name),
+            "basis": ("nominal: 114 FLOP per pair term of Eq. (7) (old and new position of the moved atom); "
+                      "the row-sum variant forms fewer, so for it this is an effective rate"),
+            "executed": executed,
+            "executed_frac": executed / PEAK[dtype] if executed else None,
+            "executed_basis": "vector FLOPs the hardware counted (SQ_INSTS_VALU_FLOPS_*), recorded per launch",
+            "traffic": rec["traffic"],
             "traffic_unit": "bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
-            "kernel": "k_sweep",
+            "kernel": "k_sweep_coop (cooperative, several workgroups per walker)" if spread else "k_sweep",
             "launch_ms_avg": float(launch_ms.mean()),
             "launch_ms_median": float(np.median(launch_ms)),
             "launch_ms_min_max": [float(launch_ms.min()), float(launch_ms.max())],
