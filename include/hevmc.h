@@ -142,16 +142,16 @@ typedef struct {
  * atom publishes its position the same way.  Such walkers use the plain form
  * (no rows; a rows argument is ignored) with 512 threads per workgroup (256
  * or 1024 if hevmc_params.threads asks for it); their local
- * energies run in a separate kernel, one workgroup per walker streaming the
- * coordinates through LDS.  hevmc_init_walkers, hevmc_sweep, hevmc_sweep_log,
+ * energies run in separate kernels that stream the coordinates through LDS,
+ * several workgroups per walker.  hevmc_init_walkers, hevmc_sweep, hevmc_sweep_log,
  * hevmc_local_energy, hevmc_footprint, hevmc_plan_launch and the ensemble
  * layer accept them; the other entry points return HEVMC_ENOFIT.  For spread
  * walkers hevmc_sweep and hevmc_sweep_log are synchronous: every wait of a
  * workgroup for the others is bounded, and a wait that gives up (a workgroup
  * stopped arriving) ends the call with HEVMC_EDEVICE and the walkers' state
  * not valid.  The library keeps a small device workspace per device for the
- * mailboxes (grow-only, held until the process ends); calls that overlap on
- * one device race.  */
+ * mailboxes and the local energy's partial sums (grow-only, held until the
+ * process ends); calls that overlap on one device race.  */
 
 /* Fills *out with the launch plan of hevmc_sweep for p.  HEVMC_ENOFIT as
  * hevmc_footprint. */

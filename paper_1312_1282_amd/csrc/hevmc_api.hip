@@ -425,6 +425,8 @@ extern "C" hevmc_status hevmc_footprint(const hevmc_params *p, size_t *lds_bytes
     return HEVMC_OK;
 }
 
+static hevmc_status spread_energy(const Launch &L, const void *coords, hevmc_walker_acc *acc, double *out, int mode);
+
 extern "C" hevmc_status hevmc_init_walkers(const hevmc_params *p, void *coords, hevmc_walker_acc *acc,
                                            double *rows, int32_t fcc_start, void *stream)
 {
@@ -441,7 +443,7 @@ extern "C" hevmc_status hevmc_init_walkers(const hevmc_params *p, void *coords, 
         if (fcc_start && (st = launched(launch_fcc_global(L, coords, nc, L.k.L / nc), "fcc kernel launch")) !=
                              HEVMC_OK)
             return st;
-        return launched(launch_energy_global(L, coords, acc, nullptr, 0), "start kernel launch");
+        return spread_energy(L, coords, acc, nullptr, 0);
     }
     return launched(launch_init(L, coords, acc, rows, fcc_start ? 1 : 0, nc, L.k.L / nc), "init kernel launch");
 }
@@ -467,16 +469,16 @@ struct MoveLog {
 // status word): one grow-only buffer per device, kept until the process ends.
 // Calls that overlap on one device would share it: they race (as calls that
 // share buffers do).
-static hevmc_status spread_workspace(size_t bytes, void **out)
+static hevmc_status spread_workspace(size_t bytes, void **out, int slot = 0)
 {
     static std::mutex mu;
-    static std::map<int, std::pair<void *, size_t>> bufs;
+    static std::map<std::pair<int, int>, std::pair<void *, size_t>> bufs;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess)
         return hip_fail(e, "hipGetDevice");
     std::lock_guard<std::mutex> g(mu);
-    auto &b = bufs[dev];
+    auto &b = bufs[{dev, slot}];
     if (b.second < bytes) {
         if (b.first) {
             e = hipDeviceSynchronize();
@@ -493,6 +495,20 @@ static hevmc_status spread_workspace(size_t bytes, void **out)
     }
     *out = b.first;
     return HEVMC_OK;
+}
+
+// The local energy of spread walkers: partial sums in a workspace of its own
+// (slot 1), then the per-walker finish.
+static hevmc_status spread_energy(const Launch &L, const void *coords, hevmc_walker_acc *acc, double *out, int mode)
+{
+    const size_t bytes = (size_t)energy_blocks(L.p.n_walkers_grid, L.k.n) * (size_t)L.p.n_walkers_grid * 5 *
+                         sizeof(double);
+    void *part = nullptr;
+    hevmc_status st = spread_workspace(bytes, &part, 1);
+    if (st != HEVMC_OK)
+        return st;
+    return launched(launch_energy_global(L, coords, acc, out, mode, static_cast<double *>(part)),
+                    "local-energy kernel launch");
 }
 
 // Polls a cooperative sweep's wait makes before it gives up: HEVMC_SPREAD_SPIN_CAP
@@ -582,8 +598,7 @@ static hevmc_status sweep_spread(const Launch &L, const hevmc_params *p, void *c
             if ((st = launched(launch_sweep_coop(Lg, c, cg, ag, (uint32_t)t, (int32_t)(te - t + 1), mstart, g),
                                "cooperative sweep launch")) != HEVMC_OK)
                 return st;
-            if (sample && (st = launched(launch_energy_global(Lg, cg, ag, nullptr, 1), "sample kernel launch")) !=
-                              HEVMC_OK)
+            if (sample && (st = spread_energy(Lg, cg, ag, nullptr, 1)) != HEVMC_OK)
                 return st;
             t = te + 1;
         }
@@ -747,7 +762,7 @@ extern "C" hevmc_status hevmc_local_energy(const hevmc_params *p, const void *co
     if (!coords || !out)
         return fail(HEVMC_EINVAL, "coords and out must be device pointers");
     if (L.spread)
-        return launched(launch_energy_global(L, coords, nullptr, out, 2), "local-energy kernel launch");
+        return spread_energy(L, coords, nullptr, out, 2);
     return launched(launch_local_energy(L, coords, out), "local-energy kernel launch");
 }
 

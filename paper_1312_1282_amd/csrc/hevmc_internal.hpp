@@ -125,7 +125,11 @@ hipError_t launch_draw_moves(const Launch &L, uint32_t t, int32_t *s, double *xi
 // cooperative kernel's workgroups per compute unit.
 hipError_t launch_sweep_coop(const Launch &L, const CoopArgs &c, void *coords, hevmc_walker_acc *acc,
                              uint32_t sweep0, int32_t nsw, uint32_t mstart, int32_t walkers);
-hipError_t launch_energy_global(const Launch &L, const void *coords, hevmc_walker_acc *acc, double *out, int mode);
+// Local energy of spread walkers (mode 0 start, 1 sample, 2 values to out),
+// with part a device buffer of energy_blocks(W, N) x W x 5 doubles.
+int energy_blocks(int n_walkers, int n);
+hipError_t launch_energy_global(const Launch &L, const void *coords, hevmc_walker_acc *acc, double *out, int mode,
+                                double *part);
 hipError_t launch_fcc_global(const Launch &L, void *coords, int nc, double a_lat);
 hipError_t coop_blocks_per_cu(const Launch &L, int *blocks_per_cu);
 

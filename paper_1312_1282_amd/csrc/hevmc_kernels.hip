@@ -1542,20 +1542,20 @@ hipError_t launch_move_delta(const Launch &L, const void *coords, const int32_t 
 // same way.  Every wait is bounded: after spin_cap polls the workgroup gives
 // up, records the timeout in *status and leaves; the others then time out in
 // turn, so the grid always drains.  Local energies of such walkers come from
-// a separate kernel with one workgroup per walker that streams the partners
-// through LDS tiles.
+// separate kernels that stream the partners through LDS tiles: partial sums
+// over blocks of atoms (several workgroups per walker), then a per-walker
+// finish that adds them in block order.
 
-// Local energy terms (or just the running totals U, V) of walker blockIdx.x,
-// with the coordinates read from device memory in tiles of `tile` atoms.
-// mode 0: start (u_run, v_run of the configuration; accumulators zeroed);
-// mode 1: a sample (accumulators, u_run, v_run reset to the fresh totals);
-// mode 2: write (E_L, V, T_PB, T_JF, T_F, U) to out[blockIdx.x][6].
-// Every ordered pair is formed: V and U are halved, and the Laplacian and
-// gradient terms of atom i run over all its partners.
+// Local energy of spread walkers in two steps, so that every compute unit
+// works even when there are fewer walkers than compute units.
+// k_energy_part: workgroup blockIdx.x = w * B + b forms, for the atoms i of
+// its block b (a run of whole NT-atom chunks) and all their partners j
+// (streamed from device memory through LDS tiles of `tile` atoms), the sums
+// (|G_i|^2, L_i, ordered V, ordered U) and a non-finite flag, into
+// part[blockIdx.x][5].  Every ordered pair is formed.
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_energy_global(KParams p, const T *__restrict__ coords,
-                                                      hevmc_walker_acc *__restrict__ accs, double *__restrict__ out,
-                                                      int mode, int tile)
+__global__ __launch_bounds__(NT) void k_energy_part(KParams p, const T *__restrict__ coords,
+                                                    double *__restrict__ part, int B, int tile)
 {
     constexpr int NW = NT / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1563,13 +1563,16 @@ __global__ __launch_bounds__(NT) void k_energy_global(KParams p, const T *__rest
     T *tx = reinterpret_cast<T *>(smem_raw);
     T *ty = tx + tile, *tz = ty + tile;
     const int n = p.n, tid = threadIdx.x;
-    const T *gx = coords + (size_t)blockIdx.x * 3 * (size_t)n;
+    const int w = (int)(blockIdx.x / (uint32_t)B), b = (int)(blockIdx.x % (uint32_t)B);
+    const int nch = (n + NT - 1) / NT, cpb = (nch + B - 1) / B;
+    const int i_begin = b * cpb * NT, i_end = min(n, (b + 1) * cpb * NT);
+    const T *gx = coords + (size_t)w * 3 * (size_t)n;
     const T *gy = gx + n, *gz = gy + n;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};   // sum |G_i|^2, sum L_i, ordered V, ordered U
     bool bad = false;
-    for (int c0 = 0; c0 < n; c0 += NT) {
+    for (int c0 = i_begin; c0 < i_end; c0 += NT) {
         const int i = c0 + tid;
-        const bool live = i < n;
+        const bool live = i < i_end;
         const T xi = live ? gx[i] : T(0), yi = live ? gy[i] : T(0), zi = live ? gz[i] : T(0);
         bad |= live && !(isfinite((double)xi) && isfinite((double)yi) && isfinite((double)zi));
         double sgx = 0.0, sgy = 0.0, sgz = 0.0, sl = 0.0, sv = 0.0, su = 0.0;
@@ -1605,17 +1608,42 @@ __global__ __launch_bounds__(NT) void k_energy_global(KParams p, const T *__rest
     }
     const bool any_bad = walker_any<NT>(bad, ebuf);
     block_sum<NT, 4>(acc, ebuf);
-    if (tid != 0)
+    if (tid == 0) {
+        double *o = part + (size_t)blockIdx.x * 5;
+        for (int q = 0; q < 4; ++q)
+            o[q] = acc[q];
+        o[4] = any_bad ? 1.0 : 0.0;
+    }
+}
+
+// k_energy_finish: thread w adds walker w's B partial sums in block order and
+// forms (E_L, V, T_PB, T_JF, T_F, U) (V and U halved: ordered pairs).
+// mode 0: start (u_run, v_run of the configuration; accumulators zeroed);
+// mode 1: a sample (accumulators, u_run, v_run reset to the fresh totals);
+// mode 2: write the six values to out[w][6].
+__global__ void k_energy_finish(KParams p, const double *__restrict__ part, int B, int n_walkers,
+                                hevmc_walker_acc *__restrict__ accs, double *__restrict__ out, int mode)
+{
+    const int w = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (w >= n_walkers)
         return;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    bool any_bad = false;
+    for (int b = 0; b < B; ++b) {
+        const double *o = part + ((size_t)w * B + b) * 5;
+        for (int q = 0; q < 4; ++q)
+            acc[q] += o[q];
+        any_bad |= o[4] != 0.0;
+    }
     const double V = 0.5 * acc[2], U = 0.5 * acc[3];
     const double tpb = -p.kappa * (acc[1] + acc[0]);
     const double el[6] = {V + tpb, V, tpb, -0.5 * p.kappa * acc[1], p.kappa * acc[0], U};
     if (mode == 2) {
         for (int q = 0; q < 6; ++q)
-            out[(size_t)blockIdx.x * 6 + q] = el[q];
+            out[(size_t)w * 6 + q] = el[q];
         return;
     }
-    hevmc_walker_acc *a = accs + blockIdx.x;
+    hevmc_walker_acc *a = accs + w;
     if (mode == 0) {
         hevmc_walker_acc z = {};
         *a = z;
@@ -1975,15 +2003,20 @@ static hipError_t coop_capacity_t(const Launch &L, int *blocks_per_cu)
 
 template <typename T, int NT>
 static hipError_t launch_energy_global_t(const Launch &L, const void *coords, hevmc_walker_acc *acc, double *out,
-                                         int mode, int tile)
+                                         int mode, int tile, double *part, int B)
 {
-    auto kern = k_energy_global<T, NT>;
+    auto kern = k_energy_part<T, NT>;
     const size_t lds = 3 * (size_t)tile * sizeof(T);
     hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(kern, dim3(L.p.n_walkers_grid), dim3(NT), lds, L.stream, L.k, (const T *)coords, acc, out,
-                       mode, tile);
+    const int W = L.p.n_walkers_grid;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(W * B)), dim3(NT), lds, L.stream, L.k, (const T *)coords, part, B, tile);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_energy_finish, dim3((unsigned)((W + 63) / 64)), dim3(64), 0, L.stream, L.k,
+                       (const double *)part, B, W, acc, out, mode);
     return hipGetLastError();
 }
 
@@ -2008,13 +2041,25 @@ hipError_t coop_blocks_per_cu(const Launch &L, int *blocks_per_cu)
     HEVMC_DISPATCH(coop_capacity_t, blocks_per_cu);
 }
 
-hipError_t launch_energy_global(const Launch &Ls, const void *coords, hevmc_walker_acc *acc, double *out, int mode)
+int energy_blocks(int n_walkers, int n)
 {
-    // 256 threads whatever the sweep's workgroup size (no spills at this size)
+    // about 2048 workgroups in all (several per compute unit), each at least
+    // one 256-atom chunk of its walker
+    const int nch = (n + 255) / 256;
+    const int want = (2048 + n_walkers - 1) / n_walkers;
+    return std::max(1, std::min(nch, want));
+}
+
+hipError_t launch_energy_global(const Launch &Ls, const void *coords, hevmc_walker_acc *acc, double *out, int mode,
+                                double *part)
+{
+    // 256 threads whatever the sweep's workgroup size (no spills at this size);
+    // 24 KB tiles, so several workgroups share a compute unit
     Launch L = Ls;
     L.threads = 256;
-    const int tile = L.fp32 ? 4096 : 2048;
-    HEVMC_DISPATCH(launch_energy_global_t, coords, acc, out, mode, tile);
+    const int tile = L.fp32 ? 2048 : 1024;
+    const int B = energy_blocks(L.p.n_walkers_grid, L.k.n);
+    HEVMC_DISPATCH(launch_energy_global_t, coords, acc, out, mode, tile, part, B);
 }
 
 hipError_t launch_fcc_global(const Launch &L, void *coords, int nc, double a_lat)

@@ -119,6 +119,49 @@ def test_spread_every_move_follows_the_oracle_fp64(threads):
     assert 0.35 < g[:, :, 1].mean() < 0.7
 
 
+def _repeat_counts(s_, wid, n):
+    """Moves of sweep 0 of walker id wid whose atom is the previous move's
+    (s_{m+1} = s_m) or the one before (s_{m+1} = s_{m-1})."""
+    s = [O.draw_move(s_, k, 0, wid)[0] for k in range(n)]
+    same = sum(s[m + 1] == s[m] for m in range(n - 1))
+    back = sum(s[m + 1] == s[m - 1] != s[m] for m in range(1, n - 1))
+    return same, back
+
+
+def test_spread_repeated_atoms_follow_the_oracle():
+    """A move of the same atom again takes its old position from the outcome
+    of the move before (nobody publishes it), and a move of the atom two
+    moves back reads the position its holder published after that move's
+    decision.  Walkers whose sweep has several of each are picked from the
+    move stream and run move by move against the oracle."""
+    n = 8000
+    s_ = osys(n)
+    picked = []
+    for wid in range(400):
+        same, back = _repeat_counts(s_, wid, n)
+        if same >= 2 and back >= 2:
+            picked.append(wid)
+        if len(picked) == 2:
+            break
+    assert len(picked) == 2
+    for wid in picked:
+        p = abi.make_params(n, 1, precision=abi.FP64, density=RHO, b=B, step_sigma=STEP, seed=17,
+                            walker_id_base=wid)
+        assert abi.plan_launch(p)["slices"] == 2
+        coords, acc = abi.alloc_state(p)
+        x0 = O.fcc_start(s_, wid)
+        coords.copy_(torch.from_numpy(x0[None]).cuda())
+        abi.init_walkers(p, coords, acc, fcc_start=False)
+        log = torch.full((1, n, 4), float("nan"), dtype=torch.float64, device="cuda")
+        abi.sweep(p, coords, acc, 0, 1, movelog=log)
+        torch.cuda.synchronize()
+        a = O.walker_init(s_, x0.copy())
+        x = x0.copy()
+        rec = O.run_walker_log(s_, wid, x, a, 0, 1, 0xFFFFFFFF, 0)
+        compare_fp64(log.cpu().numpy()[0], rec, rows_form=False)
+        assert np.max(np.abs(coords.cpu().numpy()[0] - x)) < 1e-9
+
+
 def test_spread_every_move_follows_the_oracle_fp32():
     """N = 14000 in FP32 (168 KB of coordinates, two workgroups), one walker,
     one sweep, move by move within the FP32 bounds."""
