@@ -179,6 +179,31 @@ def test_spread_every_move_follows_the_oracle_fp32():
     end, _ = compare_fp32(log.cpu().numpy()[0], o[0][0], xl, False, min_moves=n // 4, L=s_.L)
 
 
+def test_spread_ensemble_matches_the_stateless_calls():
+    """The ensemble layer runs spread walkers through the same calls: an
+    owning ensemble started from given coordinates gives the bits of
+    hevmc_init_walkers + hevmc_sweep on the same coordinates."""
+    n, W = 8000, 2
+    p = params(n, W)
+    s_ = osys(n)
+    xs = np.stack([O.fcc_start(s_, w) for w in range(W)])
+    e = abi.Ensemble(p, init_xyz=xs)
+    e.run(1, energy_every=1, measure=True)
+    e.sync()
+    a_e, x_e = e.acc(), e.coords()
+    e.close()
+    coords, acc = abi.alloc_state(p)
+    coords.copy_(torch.from_numpy(xs).cuda())
+    abi.init_walkers(p, coords, acc, fcc_start=False)
+    abi.sweep(p, coords, acc, 0, 1, 0, 1)
+    torch.cuda.synchronize()
+    a_s = abi.acc_to_numpy(acc)
+    assert np.array_equal(x_e, coords.cpu().numpy())
+    for f in abi.ACC_FIELDS + abi.ACC_INT_FIELDS:
+        assert np.array_equal(a_e[f], a_s[f]), f
+    assert np.all(a_s["n_samples"] == 1) and np.all(a_s["n_try"] == n)
+
+
 def test_spread_wait_that_gives_up_is_reported(monkeypatch):
     """A zero poll limit (forced from the host): a workgroup that finds the
     others not yet arrived gives up at once, the others give up in turn, and
