@@ -337,6 +337,20 @@ void make_kparams(const hevmc_params *p, KParams &k)
     k.h2f = (float)(h * h);
     k.c5f = (float)k.c5;
     k.u0f = (float)k.u0;
+    // FP32 form of V, HFD-B(HE) with eps and r_m folded into the constants and
+    // e^a written 2^(a log2 e): see KParams
+    {
+        const double l2e = 1.0 / std::log(2.0), s = std::sqrt(l2e);
+        k.vb = (float)(az::beta * l2e / az::rm2);
+        k.va = (float)(az::alpha * l2e / az::rm);
+        k.vl = (float)std::log2(az::epsA);
+        k.vd = (float)(az::Drm * s);
+        k.vs = (float)s;
+        k.vdr = (float)az::Drm;
+        k.vc6 = (float)az::eC6;
+        k.vc8 = (float)az::eC8;
+        k.vc10 = (float)az::eC10;
+    }
     k.sorted = 0;
     k.gr_bins = 0;
     k.gr = nullptr;

@@ -26,6 +26,11 @@ struct KParams {
     double u0;           // -2 f(L/2): u(r) = f(r) + f(L-r) + u0 (Eq. (8), as read)
     double kappa;        // hbar^2 / 2m
     float Lf, invLf, h2f, c5f, u0f;
+    // FP32 form of V with the constants folded (set on the host): eps A e^a =
+    // 2^(r (vb r - va) + vl) with a = -alpha x + beta x^2, x = r / r_m;
+    // F = 2^-((vd / r - vs)^2) for r < vdr = D r_m; dispersion coefficients
+    // vc6, vc8, vc10 on powers of 1/r^2 (eps and r_m folded in)
+    float vb, va, vl, vd, vs, vdr, vc6, vc8, vc10;
     int32_t sorted;      // sweep keeps the atoms in LDS in spatial (Morton) order
     int32_t gr_bins;     // bins of the pair histogram accumulated at each sample (0: none)
     uint64_t *gr;        // [W][gr_bins] histogram counts (device), or null
@@ -55,6 +60,13 @@ constexpr double rm2 = rm * rm;
 constexpr double Drm = D * rm;        // D / x = Drm / r
 constexpr double beta_rm2 = beta / (rm * rm);   // -alpha x + beta x^2 = beta_rm2 r^2 - alpha_rm r
 constexpr double alpha_rm = alpha / rm;
+// eps folded into the amplitudes and r_m into the dispersion coefficients
+// (the FP32 form's constants): eps C_k x^-k = eC_k w^(k/2), w = r^-2,
+// eC_k = eps C_k r_m^k
+constexpr double epsA = eps * A;
+constexpr double eC6 = eps * C6 * rm2 * rm2 * rm2;
+constexpr double eC8 = eC6 / C6 * C8 * rm2;
+constexpr double eC10 = eC6 / C6 * C10 * rm2 * rm2;
 // The repulsive exponential is skipped where its exponent is below rep_min:
 // there eps A e^a < 2.7e-18 K, under half an ulp of V itself at the distance
 // where that happens (9.27 A, V = -0.016 K).
@@ -300,7 +312,17 @@ __device__ __forceinline__ double pair_v_ri(const KParams &p, double r2, double 
 
 // FP32 form: same terms in single precision with the hardware reciprocal,
 // reciprocal square root and base-2 exponential.
-__device__ __forceinline__ float fexp(float a) { return __builtin_amdgcn_exp2f(a * 1.4426950408889634f); }
+
+// FP32 V(r) from r, 1/r and 1/r^2 with the host-folded constants of KParams
+// (no cutoff): the same terms as the FP64 form, each exponential one exp2.
+__device__ __forceinline__ float aziz_f(const KParams &p, float r, float ri, float w)
+{
+    const float rep = __builtin_amdgcn_exp2f(fmaf(r, fmaf(p.vb, r, -p.va), p.vl));
+    const float disp = w * w * w * fmaf(w, fmaf(w, p.vc10, p.vc8), p.vc6);
+    const float q = fmaf(p.vd, ri, -p.vs);
+    const float F = r < p.vdr ? __builtin_amdgcn_exp2f(-(q * q)) : 1.0f;
+    return fmaf(-F, disp, rep);
+}
 
 __device__ __forceinline__ void pair_uv(const KParams &p, float r2, float &u, float &v)
 {
@@ -309,16 +331,7 @@ __device__ __forceinline__ void pair_uv(const KParams &p, float r2, float &u, fl
     const float rpi = __builtin_amdgcn_rcpf(p.Lf - r);
     const float ri2 = ri * ri, rpi2 = rpi * rpi;
     const float uu = p.c5f * (ri2 * ri2 * ri + rpi2 * rpi2 * rpi) + p.u0f;
-    const float x = r * (float)az::inv_rm;
-    const float rep = (float)az::A * fexp(x * ((float)az::beta * x - (float)az::alpha));
-    const float y = (float)az::rm2 * ri2;
-    const float disp = y * y * y * ((float)az::C6 + y * ((float)az::C8 + y * (float)az::C10));
-    float F = 1.0f;
-    if (x < (float)az::D) {
-        const float q = (float)az::Drm * ri - 1.0f;
-        F = fexp(-(q * q));
-    }
-    const float vv = (float)az::eps * (rep - F * disp);
+    const float vv = aziz_f(p, r, ri, ri2);
     const bool in = r2 <= p.h2f;
     u = in ? uu : 0.0f;
     v = in ? vv : 0.0f;
@@ -344,17 +357,7 @@ __device__ __forceinline__ float pair_u_in(const KParams &p, float r2, float ri,
 
 __device__ __forceinline__ float pair_v_ri(const KParams &p, float r2, float ri)
 {
-    const float r = r2 * ri;
-    const float x = r * (float)az::inv_rm;
-    const float rep = (float)az::A * fexp(x * ((float)az::beta * x - (float)az::alpha));
-    const float y = (float)az::rm2 * (ri * ri);
-    const float disp = y * y * y * ((float)az::C6 + y * ((float)az::C8 + y * (float)az::C10));
-    float F = 1.0f;
-    if (x < (float)az::D) {
-        const float q = (float)az::Drm * ri - 1.0f;
-        F = fexp(-(q * q));
-    }
-    const float vv = (float)az::eps * (rep - F * disp);
+    const float vv = aziz_f(p, r2 * ri, ri, ri * ri);
     return r2 <= p.h2f ? vv : 0.0f;
 }
 
@@ -443,16 +446,7 @@ __device__ __forceinline__ void pair_energy(const KParams &p, float r2, ETerms &
     const float uu = p.c5f * (ri5 + rpi5) + p.u0f;
     const float du = -5.0f * p.c5f * (ri6 - rpi6);
     const float d2u = 30.0f * p.c5f * (ri6 * ri + rpi6 * rpi);
-    const float x = r * (float)az::inv_rm;
-    const float rep = (float)az::A * fexp(x * ((float)az::beta * x - (float)az::alpha));
-    const float y = (float)az::rm2 * ri2;
-    const float disp = y * y * y * ((float)az::C6 + y * ((float)az::C8 + y * (float)az::C10));
-    float F = 1.0f;
-    if (x < (float)az::D) {
-        const float q = (float)az::Drm * ri - 1.0f;
-        F = fexp(-(q * q));
-    }
-    const float vv = (float)az::eps * (rep - F * disp);
+    const float vv = aziz_f(p, r, ri, ri2);
     const float dur = du * ri;
     const bool in = r2 <= p.h2f;
     e.r = (double)r;

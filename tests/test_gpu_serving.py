@@ -119,16 +119,18 @@ def test_replicated_server_alone_and_in_mix_and_energy():
 
 
 def test_freed_slots_and_admission_during_flight_keep_results():
-    """Continuous batching proper: one request per class at a time and a pool
-    of 64 slots per class, so later requests of a class wait for an earlier one
-    to retire and take its freed slots, and are admitted while the other class
-    has a launch in flight; staggered real-time arrivals.  Every result equals
-    the same request served alone, bit for bit."""
-    mk = lambda: [_req(0, 108, 64, abi.FP64, 0.0200, 2.8, 41), _req(1, 256, 64, abi.FP32, 0.0215, 3.0, 42),
-                  _req(2, 108, 64, abi.FP64, 0.0230, 3.1, 43), _req(3, 256, 48, abi.FP32, 0.0205, 2.9, 44),
+    """Continuous batching proper: one request per class at a time, so later
+    requests of a class wait for an earlier one to retire and take its freed
+    slots, and are admitted while the other class has a launch in flight (its
+    walkers are large enough, N=1024 and 256 of them, that its launches take
+    milliseconds and follow each other back to back); staggered real-time
+    arrivals.  Every result equals the same request served alone, bit for
+    bit."""
+    mk = lambda: [_req(0, 108, 64, abi.FP64, 0.0200, 2.8, 41), _req(1, 1024, 256, abi.FP32, 0.0215, 3.0, 42),
+                  _req(2, 108, 64, abi.FP64, 0.0230, 3.1, 43), _req(3, 1024, 192, abi.FP32, 0.0205, 2.9, 44),
                   _req(4, 108, 32, abi.FP64, 0.0219, 2.94, 45)]
     kw = dict(target_se=4e-3, equil=20, check_every=10, min_samples=2, quantum=5, max_requests_per_class=1,
-              slots_per_class=64)
+              slots_per_class=256)
     reqs = mk()
     for k, r in enumerate(reqs):
         r.arrival = 0.02 * k
