@@ -27,6 +27,15 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
+def test_status_codes_match_the_header():
+    """Every hevmc_status the header defines has the binding's name and value."""
+    with open(os.path.join(ROOT, "include", "hevmc.h")) as fh:
+        text = fh.read()
+    body = text[text.index("typedef enum {"):text.index("} hevmc_status;")]
+    codes = {int(v): k for k, v in re.findall(r"(HEVMC_[A-Z]+)\s*=\s*(-?\d+)", body)}
+    assert codes == abi.STATUS
+
+
 def test_parameter_struct_layouts():
     assert C.sizeof(abi.Params) == 72
     assert C.sizeof(abi.WalkerAcc) == 160
