@@ -110,8 +110,8 @@ double or_f(const or_system *sys, double r)
 
 /* Eq. (8), Reading: the printed ratio form is garbled (taken literally it
  * diverges to +infinity at short range, contradicting the statement after
- * Eq. (9) that f prevents core overlap, and "1 for r > L/2" is the value of a
- * pair factor, not of its logarithm).  Read as the symmetrization of the pair
+ * Eq. (9) that f prevents core overlap, and its value of one beyond L/2 is
+ * that of a pair factor, not of its logarithm).  Read as the symmetrization of the pair
  * factor exp(f):  exp(u(r)) = exp(f(r)) exp(f(L-r)) / exp(f(L/2))^2, i.e.
  *   u(r) = f(r) + f(L - r) - 2 f(L/2)   for r <= L/2,   0 beyond,
  * which gives u(L/2) = u'(L/2) = 0: the continuous first derivative and absent
