@@ -522,6 +522,57 @@ def test_a_second_thread_on_a_busy_ensemble_gets_ebusy():
     e.close()
 
 
+@pytest.mark.parametrize("precision,threads", [(abi.FP64, 64), (abi.FP64, 256), (abi.FP32, 128)])
+def test_ideal_gas_b_zero_accepts_every_move(precision, threads):
+    """The degenerate trial function b = 0 (u = 0, psi constant): every
+    Eq. (7) sum is zero, so Eq. (5) accepts every move, and the walkers do
+    the oracle's random walk; the local energy is V alone (T = 0)."""
+    n, W, sweeps = 108, 4, 3
+    p = gparams(n, W, precision=precision, threads=threads, b=0.0)
+    coords, acc = abi.alloc_state(p)
+    rows = abi.alloc_rows(p)
+    abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
+    abi.sweep(p, coords, acc, 0, sweeps, 0, 1, rows=rows)
+    torch.cuda.synchronize()
+    a = abi.acc_to_numpy(acc)
+    assert np.all(a["n_acc"] == n * sweeps) and np.all(a["n_try"] == n * sweeps)
+    assert np.all(a["sum_tpb"] == 0.0) and np.all(a["sum_tjf"] == 0.0) and np.all(a["sum_tf"] == 0.0)
+    fp32 = precision == abi.FP32
+    s_ = osys(n, b=0.0, fp32=fp32)
+    xs = coords.cpu().numpy().astype(np.float64)
+    for w in range(W):
+        x = O.fcc_start(s_, w)
+        if fp32:
+            x = x.astype(np.float32).astype(np.float64)
+        for t in range(sweeps):
+            for k in range(n):
+                sk, _, d = O.draw_move(s_, k, t, w)
+                x[:, sk] = O.trial_position(s_, x, sk, d)
+                if fp32:
+                    x[:, sk] = x[:, sk].astype(np.float32).astype(np.float64)
+        tol = 1e-9 if not fp32 else 1e-4
+        gap = np.abs(xs[w] - x)
+        gap = np.minimum(gap, s_.L - gap)
+        assert gap.max() < tol, (w, gap.max())
+        el, scale = O.local_energy(s_, xs[w])
+        assert el[2] == 0.0 and el[3] == 0.0 and el[4] == 0.0
+
+
+def test_zero_sweeps_change_nothing():
+    """A sweep call of zero sweeps leaves coordinates, accumulators and rows
+    as they were, bit for bit."""
+    p = gparams(256, 8, threads=128)
+    coords, acc = abi.alloc_state(p)
+    rows = abi.alloc_rows(p)
+    abi.init_walkers(p, coords, acc, fcc_start=True, rows=rows)
+    abi.sweep(p, coords, acc, 0, 2, 0, 1, rows=rows)
+    torch.cuda.synchronize()
+    c0, a0, r0 = coords.clone(), acc.clone(), rows.clone()
+    abi.sweep(p, coords, acc, 2, 0, 0, 1, rows=rows)
+    torch.cuda.synchronize()
+    assert torch.equal(coords, c0) and torch.equal(acc, a0) and torch.equal(rows, r0)
+
+
 @pytest.mark.parametrize("wl,threads,variant,spatial", [
     (configs.C2_N2048_FP64, 256, abi.VARIANT_ROWS, 1),
     (configs.C3_N2048_FP32, 256, abi.VARIANT_ROWS, 1),
