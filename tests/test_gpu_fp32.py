@@ -59,9 +59,11 @@ def test_fp32_move_sums(n, threads):
         assert within(out[w, 1], dv, sv, 1e-5), (w, out[w, 1], dv, sv)
 
 
-@pytest.mark.parametrize("n,threads", [(108, 128), (864, 128), (2048, 256)])
+@pytest.mark.parametrize("n,threads", [(108, 128), (864, 128), (2048, 256), (14000, 0)])
 def test_fp32_local_energy(n, threads):
-    W = 4
+    """Also N = 14000, a walker spread over two workgroups, whose local energy
+    runs in the split kernels (blocks of atoms, then the per-walker finish)."""
+    W = 4 if n <= 2048 else 2
     s_ = osys32(n)
     xs = np.stack([grid_config(n, s_.L, seed=400 + n + w, dtype=np.float32) for w in range(W)])
     p = abi.make_params(n, W, precision=abi.FP32, threads=threads)

@@ -162,6 +162,30 @@ def test_spread_repeated_atoms_follow_the_oracle():
         assert np.max(np.abs(coords.cpu().numpy()[0] - x)) < 1e-9
 
 
+def test_spread_sequential_order_follows_the_oracle():
+    """Atoms moved in label order (s = k, Sec. 2's alternative to random
+    selection): the next move's atom is always another one, so every old
+    position comes from the mailbox; one sweep move by move."""
+    n = 8000
+    p = abi.make_params(n, 1, precision=abi.FP64, density=RHO, b=B, step_sigma=STEP, seed=17,
+                        order=abi.SELECT_SEQUENTIAL)
+    assert abi.plan_launch(p)["slices"] == 2
+    coords, acc = abi.alloc_state(p)
+    abi.init_walkers(p, coords, acc, fcc_start=True)
+    log = torch.full((1, n, 4), float("nan"), dtype=torch.float64, device="cuda")
+    abi.sweep(p, coords, acc, 0, 1, movelog=log)
+    torch.cuda.synchronize()
+    s_ = O.system(n, O.box_side(n, RHO), B, hbar2_over_m=configs.HBAR2_OVER_M, step_sigma=STEP, seed=17,
+                  order=1)
+    x = O.fcc_start(s_, 0)
+    a = O.walker_init(s_, x)
+    rec = O.run_walker_log(s_, 0, x, a, 0, 1, 0xFFFFFFFF, 0)
+    g = log.cpu().numpy()[0]
+    assert np.array_equal(g[:, 0], np.arange(n, dtype=np.float64))
+    compare_fp64(g, rec, rows_form=False)
+    assert np.max(np.abs(coords.cpu().numpy()[0] - x)) < 1e-9
+
+
 def test_spread_every_move_follows_the_oracle_fp32():
     """N = 14000 in FP32 (168 KB of coordinates, two workgroups), one walker,
     one sweep, move by move within the FP32 bounds."""
