@@ -48,6 +48,10 @@ def test_spread_plans():
     for t in (256, 1024):
         assert abi.plan_launch(params(8000, 2, threads=t))["threads"] == t
     assert abi.plan_launch(params(40960, 1, abi.FP32))["slices"] == 4
+    # beyond 14 slices' LDS the walker does not fit at all
+    with pytest.raises(abi.HevmcError) as ei:
+        abi.plan_launch(params(100000, 1))
+    assert ei.value.code == -3
     assert abi.plan_launch(params(14000, 1, abi.FP32))["slices"] == 2
     assert abi.plan_launch(params(2048, 1))["slices"] == 1
     assert abi.plan_launch(params(13000, 1, abi.FP32))["slices"] == 1   # rows in registers, one workgroup
