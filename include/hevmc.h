@@ -144,8 +144,10 @@ typedef struct {
  * or 1024 if hevmc_params.threads asks for it); their local
  * energies run in separate kernels that stream the coordinates through LDS,
  * several workgroups per walker.  hevmc_init_walkers, hevmc_sweep, hevmc_sweep_log,
- * hevmc_local_energy, hevmc_footprint, hevmc_plan_launch and the ensemble
- * layer accept them; the other entry points return HEVMC_ENOFIT.  For spread
+ * hevmc_sweep_gr, hevmc_sweep_trace (histogram and records formed by those
+ * local-energy kernels), hevmc_local_energy, hevmc_footprint,
+ * hevmc_plan_launch and the ensemble layer accept them; the other entry
+ * points return HEVMC_ENOFIT.  For spread
  * walkers hevmc_sweep and hevmc_sweep_log are synchronous: every wait of a
  * workgroup for the others is bounded, and a wait that gives up (a workgroup
  * stopped arriving) ends the call with HEVMC_EDEVICE and the walkers' state
@@ -212,8 +214,9 @@ hevmc_status hevmc_sweep(const hevmc_params *p, void *coords, hevmc_walker_acc *
  * Normalisation: g(r_b) = counts_b / (samples * N/2 * (N/L^3) * shell volume of
  * bin b).  gr = NULL is hevmc_sweep.  The sweep's results are bitwise the same
  * with or without the histogram.  HEVMC_EINVAL for gr_bins outside
- * [1, HEVMC_MAX_GR_BINS]; HEVMC_ENOFIT if the walker and the bins do not fit
- * in one workgroup's LDS. */
+ * [1, HEVMC_MAX_GR_BINS]; HEVMC_ENOFIT if the walker fits one workgroup's LDS
+ * but not with the bins beside it (a walker that fits no workgroup at all is
+ * spread, see below, and its local-energy kernels form the histogram). */
 hevmc_status hevmc_sweep_gr(const hevmc_params *p, void *coords, hevmc_walker_acc *acc, double *rows,
                             uint64_t *gr, int32_t gr_bins, uint32_t sweep0, int32_t n_sweeps,
                             uint32_t measure_start, int32_t energy_every, void *stream);

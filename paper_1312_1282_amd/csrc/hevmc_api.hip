@@ -233,8 +233,12 @@ hevmc_status plan(const hevmc_params *p, void *stream, Launch &L, int32_t gr_bin
     const size_t need_rows = rows_lds_bytes(p);
     const size_t align16 = 15;
     if (need_plain > max_dyn || (wave_mode && per_group * ((need_plain + align16) & ~align16) > max_dyn)) {
-        if (allow_spread && gr_bins == 0 && !wave_mode)
-            return plan_spread(p, stream, L, d);
+        if (allow_spread && !wave_mode) {
+            // a spread walker's histogram is formed by its local-energy kernels
+            st = plan_spread(p, stream, L, d);
+            L.k.gr_bins = gr_bins;
+            return st;
+        }
         return fail(HEVMC_ENOFIT, "walker of %d atoms needs %zu B of LDS; a workgroup can have %zu B", p->n,
                     need_plain * per_group, max_dyn);
     }
@@ -580,6 +584,10 @@ static hevmc_status sweep_spread(const Launch &L, const hevmc_params *p, void *c
         Launch Lg = L;
         Lg.p.n_walkers_grid = g;
         Lg.k.wid_base = L.k.wid_base + (uint32_t)w0;
+        if (L.k.gr)
+            Lg.k.gr = L.k.gr + (size_t)w0 * (size_t)L.k.gr_bins;
+        if (L.k.trace)
+            Lg.k.trace = L.k.trace + (size_t)w0 * (size_t)L.k.trace_cap * 6;
         if (mlog.log && w0 < mlog.walkers) {
             Lg.k.movelog = mlog.log + (size_t)w0 * (size_t)mlog.cap * 4;
             Lg.k.log_walkers = mlog.walkers - w0;
@@ -641,7 +649,7 @@ static hevmc_status sweep_with(const hevmc_params *p, void *coords, hevmc_walker
     if (trace && trace_cap < 1)
         return fail(HEVMC_EINVAL, "trace_cap = %d must be >= 1", trace_cap);
     Launch L;
-    hevmc_status st = plan(p, stream, L, gr ? gr_bins : 0, !gr && !trace);
+    hevmc_status st = plan(p, stream, L, gr ? gr_bins : 0, true);
     if (st != HEVMC_OK)
         return st;
     L.k.gr = gr;

@@ -1552,8 +1552,11 @@ hipError_t launch_move_delta(const Launch &L, const void *coords, const int32_t 
 // its block b (a run of whole NT-atom chunks) and all their partners j
 // (streamed from device memory through LDS tiles of `tile` atoms), the sums
 // (|G_i|^2, L_i, ordered V, ordered U) and a non-finite flag, into
-// part[blockIdx.x][5].  Every ordered pair is formed.
-template <typename T, int NT>
+// part[blockIdx.x][5].  Every ordered pair is formed.  HIST: each unordered
+// pair (i < j) inside the cutoff is also counted in the pair-distance
+// histogram of walker w (p.gr, p.gr_bins bins of [0, L/2], the binning of
+// the one-workgroup sweep), through an LDS copy and integer atomics.
+template <typename T, int NT, bool HIST>
 __global__ __launch_bounds__(NT) void k_energy_part(KParams p, const T *__restrict__ coords,
                                                     double *__restrict__ part, int B, int tile)
 {
@@ -1568,6 +1571,12 @@ __global__ __launch_bounds__(NT) void k_energy_part(KParams p, const T *__restri
     const int i_begin = b * cpb * NT, i_end = min(n, (b + 1) * cpb * NT);
     const T *gx = coords + (size_t)w * 3 * (size_t)n;
     const T *gy = gx + n, *gz = gy + n;
+    const int nb = HIST ? p.gr_bins : 0;
+    const double bin_scale = (double)nb * 2.0 * p.invL;   // bins per Angstrom
+    uint32_t *hist = HIST ? reinterpret_cast<uint32_t *>(smem_raw + 3 * (size_t)tile * sizeof(T)) : nullptr;
+    if constexpr (HIST)
+        for (int q = tid; q < nb; q += NT)
+            hist[q] = 0u;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};   // sum |G_i|^2, sum L_i, ordered V, ordered U
     bool bad = false;
     for (int c0 = i_begin; c0 < i_end; c0 += NT) {
@@ -1591,14 +1600,18 @@ __global__ __launch_bounds__(NT) void k_energy_part(KParams p, const T *__restri
                 const T dx = min_image(xi - tx[q], p);
                 const T dy = min_image(yi - ty[q], p);
                 const T dz = min_image(zi - tz[q], p);
+                const T r2 = dx * dx + dy * dy + dz * dz;
                 ETerms e;
-                pair_energy(p, dx * dx + dy * dy + dz * dz, e);
+                pair_energy(p, r2, e);
                 sgx += e.dur * (double)dx;
                 sgy += e.dur * (double)dy;
                 sgz += e.dur * (double)dz;
                 sl += e.lap;
                 sv += e.v;
                 su += e.u;
+                if constexpr (HIST)
+                    if (i < j0 + q && pair_inside(p, r2))
+                        atomicAdd(&hist[min(nb - 1, (int)(e.r * bin_scale))], 1u);
             }
         }
         acc[0] += sgx * sgx + sgy * sgy + sgz * sgz;
@@ -1608,6 +1621,13 @@ __global__ __launch_bounds__(NT) void k_energy_part(KParams p, const T *__restri
     }
     const bool any_bad = walker_any<NT>(bad, ebuf);
     block_sum<NT, 4>(acc, ebuf);
+    if constexpr (HIST) {
+        __syncthreads();
+        uint64_t *grw = p.gr + (size_t)w * (size_t)nb;
+        for (int q = tid; q < nb; q += NT)
+            if (hist[q])
+                atomicAdd(reinterpret_cast<unsigned long long *>(&grw[q]), (unsigned long long)hist[q]);
+    }
     if (tid == 0) {
         double *o = part + (size_t)blockIdx.x * 5;
         for (int q = 0; q < 4; ++q)
@@ -1648,6 +1668,10 @@ __global__ void k_energy_finish(KParams p, const double *__restrict__ part, int 
         hevmc_walker_acc z = {};
         *a = z;
     } else {
+        // the sample's record, at its index among the walker's samples
+        if (p.trace && a->n_samples < (int64_t)p.trace_cap)
+            for (int q = 0; q < 6; ++q)
+                p.trace[((size_t)w * (size_t)p.trace_cap + (size_t)a->n_samples) * 6 + q] = el[q];
         nsum(a->sum_e, a->c_e, el[0]);
         nsum(a->sum_e2, a->c_e2, el[0] * el[0]);
         nsum(a->sum_v, a->c_v, el[1]);
@@ -2005,8 +2029,10 @@ template <typename T, int NT>
 static hipError_t launch_energy_global_t(const Launch &L, const void *coords, hevmc_walker_acc *acc, double *out,
                                          int mode, int tile, double *part, int B)
 {
-    auto kern = k_energy_part<T, NT>;
-    const size_t lds = 3 * (size_t)tile * sizeof(T);
+    // the pair histogram at samples (mode 1) when the sweep asks for one
+    const bool hist = mode == 1 && L.k.gr && L.k.gr_bins > 0;
+    auto kern = hist ? k_energy_part<T, NT, true> : k_energy_part<T, NT, false>;
+    const size_t lds = 3 * (size_t)tile * sizeof(T) + (hist ? (size_t)L.k.gr_bins * sizeof(uint32_t) : 0);
     hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess)
         return e;
@@ -2015,7 +2041,10 @@ static hipError_t launch_energy_global_t(const Launch &L, const void *coords, he
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_energy_finish, dim3((unsigned)((W + 63) / 64)), dim3(64), 0, L.stream, L.k,
+    KParams kf = L.k;
+    if (mode != 1)
+        kf.trace = nullptr;   // records are written at samples only
+    hipLaunchKernelGGL(k_energy_finish, dim3((unsigned)((W + 63) / 64)), dim3(64), 0, L.stream, kf,
                        (const double *)part, B, W, acc, out, mode);
     return hipGetLastError();
 }

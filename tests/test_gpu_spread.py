@@ -232,6 +232,47 @@ def test_spread_ensemble_matches_the_stateless_calls():
     assert np.all(a_s["n_samples"] == 1) and np.all(a_s["n_try"] == n)
 
 
+def test_spread_trace_and_pair_histogram_follow_the_oracle():
+    """Per-sample records (hevmc_sweep_trace) and the pair histogram
+    (hevmc_sweep_gr) of spread walkers come from their local-energy kernels:
+    both follow the oracle's chain over two sampled sweeps, and neither
+    changes the chain."""
+    n, W, sweeps, nb, cap = 8000, 2, 2, 80, 4
+    p = params(n, W)
+
+    def run(trace=None, gr=None):
+        coords, acc = abi.alloc_state(p)
+        abi.init_walkers(p, coords, acc, fcc_start=True)
+        abi.sweep(p, coords, acc, 0, sweeps, 0, 1, trace=trace, gr=gr)
+        torch.cuda.synchronize()
+        return coords.cpu().numpy(), abi.acc_to_numpy(acc)
+
+    tr = torch.full((W, cap, 6), -1.0, dtype=torch.float64, device="cuda")
+    gr = torch.zeros((W, nb), dtype=torch.int64, device="cuda")
+    x_t, a_t = run(trace=tr)
+    x_g, a_g = run(gr=gr)
+    x_0, a_0 = run()
+    assert np.array_equal(x_t, x_0) and np.array_equal(x_g, x_0)
+    assert a_t.tobytes() == a_0.tobytes() and a_g.tobytes() == a_0.tobytes()
+    tr, gr = tr.cpu().numpy(), gr.cpu().numpy()
+    s_ = osys(n)
+    for w in range(W):
+        x = O.fcc_start(s_, w)
+        a = O.walker_init(s_, x)
+        rec, ref, edge = [], np.zeros(nb, dtype=np.int64), np.zeros(nb + 1, dtype=np.int64)
+        for t in range(sweeps):
+            O.run_walker(s_, w, x, a, t, 1, 0, 1)
+            rec.append(O.local_energy(s_, x)[0])
+            h, e = O.pair_histogram(s_, x, nb, rel_window=1e-8)
+            ref += np.asarray(h, dtype=np.int64)
+            edge += np.asarray(e, dtype=np.int64)
+        np.testing.assert_allclose(tr[w, :sweeps], np.array(rec), rtol=1e-10, atol=1e-8)
+        assert np.all(tr[w, sweeps:] == -1.0)
+        slack = edge[:-1] + edge[1:]
+        assert np.all(np.abs(gr[w] - ref) <= slack), (w, np.nonzero(np.abs(gr[w] - ref) > slack)[0][:5])
+        assert ref.sum() > 0 and abs(int(gr[w].sum()) - int(ref.sum())) <= int(edge[-1])
+
+
 def test_spread_wait_that_gives_up_is_reported(monkeypatch):
     """A zero poll limit (forced from the host): a workgroup that finds the
     others not yet arrived gives up at once, the others give up in turn, and
