@@ -31,6 +31,12 @@ struct KParams {
     // F = 2^-((vd / r - vs)^2) for r < vdr = D r_m; dispersion coefficients
     // vc6, vc8, vc10 on powers of 1/r^2 (eps and r_m folded in)
     float vb, va, vl, vd, vs, vdr, vc6, vc8, vc10;
+    // Taylor coefficients 1/12!, 1/11!, ..., 1/3! of the FP64 exponential
+    // (exp_neg), copied from kExpTaylor on the host.  As kernel arguments they
+    // sit in scalar registers, where each Horner step takes its coefficient as
+    // the addend of one FMA; compile-time constants would be held in vector
+    // registers and copied before every step.
+    double ex[10];
     int32_t sorted;      // sweep keeps the atoms in LDS in spatial (Morton) order
     int32_t gr_bins;     // bins of the pair histogram accumulated at each sample (0: none)
     uint64_t *gr;        // [W][gr_bins] histogram counts (device), or null
@@ -72,6 +78,13 @@ constexpr double eC10 = eC6 / C6 * C10 * rm2 * rm2;
 // where that happens (9.27 A, V = -0.016 K).
 constexpr double rep_min = -55.0;
 }  // namespace az
+
+// 1/k! for k = 12, 11, ..., 3: the Taylor coefficients of exp_neg.
+constexpr double kExpTaylor[10] = {
+    2.08767569878680989792e-09, 2.50521083854417187751e-08, 2.75573192239858906526e-07,
+    2.75573192239858906526e-06, 2.48015873015873015873e-05, 1.98412698412698412698e-04,
+    1.38888888888888888889e-03, 8.33333333333333333333e-03, 4.16666666666666666667e-02,
+    1.66666666666666666667e-01};
 
 // --------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64 products.
@@ -198,22 +211,17 @@ __device__ __forceinline__ double rsq_nr(double x)
 // exact), e^f by its Taylor series to degree 12 (truncation < 2e-16 relative),
 // scaled by 2^k.  For a below about -745 the scaling underflows to zero, the
 // value of e^a in FP64 (a = -inf, the distance-zero pair of an atom with
-// itself, gives NaN, which the callers' masks discard).
-__device__ __forceinline__ double exp_neg(double a)
+// itself, gives NaN, which the callers' masks discard).  The coefficients of
+// degrees 12 .. 3 come from p.ex (= kExpTaylor).
+__device__ __forceinline__ double exp_neg(const KParams &p, double a)
 {
     const double k = rint(a * 1.4426950408889634);
     double f = fma(-k, 6.93147180369123816490e-01, a);
     f = fma(-k, 1.90821492927058770002e-10, f);
-    double q = 2.08767569878680989792e-09;        // 1/12!
-    q = fma(q, f, 2.50521083854417187751e-08);    // 1/11!
-    q = fma(q, f, 2.75573192239858906526e-07);    // 1/10!
-    q = fma(q, f, 2.75573192239858906526e-06);    // 1/9!
-    q = fma(q, f, 2.48015873015873015873e-05);    // 1/8!
-    q = fma(q, f, 1.98412698412698412698e-04);    // 1/7!
-    q = fma(q, f, 1.38888888888888888889e-03);    // 1/6!
-    q = fma(q, f, 8.33333333333333333333e-03);    // 1/5!
-    q = fma(q, f, 4.16666666666666666667e-02);    // 1/4!
-    q = fma(q, f, 1.66666666666666666667e-01);    // 1/3!
+    double q = p.ex[0];
+#pragma unroll
+    for (int j = 1; j < 10; ++j)
+        q = fma(q, f, p.ex[j]);
     q = fma(q, f, 0.5);
     q = fma(q, f, 1.0);
     q = fma(q, f, 1.0);
@@ -245,14 +253,14 @@ __device__ __forceinline__ void pair_uv(const KParams &p, double r2, double &u, 
     const double ea = fma(az::beta_rm2, r2, -(az::alpha_rm * r));
     double rep = 0.0;
     if (ea > az::rep_min)
-        rep = az::A * exp_neg(ea);
+        rep = az::A * exp_neg(p, ea);
     const double y = az::rm2 * ri2;                   // x^-2
     const double y2 = y * y;
     const double disp = y2 * y * fma(y, fma(y, az::C10, az::C8), az::C6);
     double F = 1.0;
     if (r < az::Drm) {
         const double q = fma(az::Drm, ri, -1.0);
-        F = exp_neg(-(q * q));
+        F = exp_neg(p, -(q * q));
     }
     const double vv = az::eps * fma(-F, disp, rep);
     const bool in = r2 <= p.h2;
@@ -297,17 +305,104 @@ __device__ __forceinline__ double pair_v_ri(const KParams &p, double r2, double 
     const double ea = fma(az::beta_rm2, r2, -(az::alpha_rm * r));
     double rep = 0.0;
     if (ea > az::rep_min)
-        rep = az::A * exp_neg(ea);
+        rep = az::A * exp_neg(p, ea);
     const double y = az::rm2 * (ri * ri);
     const double y2 = y * y;
     const double disp = y2 * y * fma(y, fma(y, az::C10, az::C8), az::C6);
     double F = 1.0;
     if (r < az::Drm) {
         const double q = fma(az::Drm, ri, -1.0);
-        F = exp_neg(-(q * q));
+        F = exp_neg(p, -(q * q));
     }
     const double vv = az::eps * fma(-F, disp, rep);
     return keep_or_tiny(r2 <= p.h2, vv);
+}
+
+// FP64: V at two distances (a moved atom's old and new position against one
+// partner), each bitwise equal to pair_v_ri.  An exponential is formed for
+// both distances when either needs it (the other's value is discarded), so
+// the two dependent Horner chains run interleaved in one branch instead of
+// one after the other in two.
+__device__ __forceinline__ void pair_v_ri2(const KParams &p, double r2a, double ria, double r2b, double rib,
+                                           double &va, double &vb)
+{
+    const double ra = r2a * ria, rb = r2b * rib;
+    const double eaa = fma(az::beta_rm2, r2a, -(az::alpha_rm * ra));
+    const double eab = fma(az::beta_rm2, r2b, -(az::alpha_rm * rb));
+    const bool ka = eaa > az::rep_min, kb = eab > az::rep_min;
+    double repa = 0.0, repb = 0.0;
+    if (ka || kb) {
+        const double xa = exp_neg(p, eaa), xb = exp_neg(p, eab);
+        repa = ka ? az::A * xa : 0.0;
+        repb = kb ? az::A * xb : 0.0;
+    }
+    const double ya = az::rm2 * (ria * ria), yb = az::rm2 * (rib * rib);
+    const double ya2 = ya * ya, yb2 = yb * yb;
+    const double dispa = ya2 * ya * fma(ya, fma(ya, az::C10, az::C8), az::C6);
+    const double dispb = yb2 * yb * fma(yb, fma(yb, az::C10, az::C8), az::C6);
+    const bool da = ra < az::Drm, db = rb < az::Drm;
+    double Fa = 1.0, Fb = 1.0;
+    if (da || db) {
+        const double qa = fma(az::Drm, ria, -1.0), qb = fma(az::Drm, rib, -1.0);
+        const double xa = exp_neg(p, -(qa * qa)), xb = exp_neg(p, -(qb * qb));
+        Fa = da ? xa : 1.0;
+        Fb = db ? xb : 1.0;
+    }
+    va = keep_or_tiny(r2a <= p.h2, az::eps * fma(-Fa, dispa, repa));
+    vb = keep_or_tiny(r2b <= p.h2, az::eps * fma(-Fb, dispb, repb));
+}
+
+// pair_v_ri2 in three phases, for callers that hold several such pairs:
+// vp_pre forms everything but the exponentials, vp_exp the exponentials
+// (the two branches), vp_post the two values.  Running every pair's vp_pre,
+// then every vp_exp, then every vp_post interleaves the pairs' arithmetic
+// outside the branches.  The values are bitwise those of pair_v_ri2.
+struct VPair {
+    double disa, disb, eaa, eab, qa, qb, repa, repb, Fa, Fb;
+    bool ka, kb, da, db, ina, inb;
+};
+
+__device__ __forceinline__ void vp_pre(const KParams &p, double r2a, double ria, double r2b, double rib, VPair &v)
+{
+    const double ra = r2a * ria, rb = r2b * rib;
+    v.eaa = fma(az::beta_rm2, r2a, -(az::alpha_rm * ra));
+    v.eab = fma(az::beta_rm2, r2b, -(az::alpha_rm * rb));
+    v.ka = v.eaa > az::rep_min;
+    v.kb = v.eab > az::rep_min;
+    const double ya = az::rm2 * (ria * ria), yb = az::rm2 * (rib * rib);
+    const double ya2 = ya * ya, yb2 = yb * yb;
+    v.disa = ya2 * ya * fma(ya, fma(ya, az::C10, az::C8), az::C6);
+    v.disb = yb2 * yb * fma(yb, fma(yb, az::C10, az::C8), az::C6);
+    v.da = ra < az::Drm;
+    v.db = rb < az::Drm;
+    v.qa = fma(az::Drm, ria, -1.0);
+    v.qb = fma(az::Drm, rib, -1.0);
+    v.ina = r2a <= p.h2;
+    v.inb = r2b <= p.h2;
+}
+
+__device__ __forceinline__ void vp_exp(const KParams &p, VPair &v)
+{
+    v.repa = 0.0;
+    v.repb = 0.0;
+    if (v.ka || v.kb) {
+        const double xa = exp_neg(p, v.eaa), xb = exp_neg(p, v.eab);
+        v.repa = v.ka ? az::A * xa : 0.0;
+        v.repb = v.kb ? az::A * xb : 0.0;
+    }
+    v.Fa = 1.0;
+    v.Fb = 1.0;
+    if (v.da || v.db) {
+        const double xa = exp_neg(p, -(v.qa * v.qa)), xb = exp_neg(p, -(v.qb * v.qb));
+        v.Fa = v.da ? xa : 1.0;
+        v.Fb = v.db ? xb : 1.0;
+    }
+}
+
+__device__ __forceinline__ void vp_post(const VPair &v, double &va, double &vb)
+{
+    va = keep_or_tiny(v.ina, az::eps * fma(-v.Fa, v.disa, v.repa));
+    vb = keep_or_tiny(v.inb, az::eps * fma(-v.Fb, v.disb, v.repb));
 }
 
 // FP32 form: same terms in single precision with the hardware reciprocal,
@@ -361,6 +456,13 @@ __device__ __forceinline__ float pair_v_ri(const KParams &p, float r2, float ri)
     return r2 <= p.h2f ? vv : 0.0f;
 }
 
+__device__ __forceinline__ void pair_v_ri2(const KParams &p, float r2a, float ria, float r2b, float rib, float &va,
+                                           float &vb)
+{
+    va = pair_v_ri(p, r2a, ria);
+    vb = pair_v_ri(p, r2b, rib);
+}
+
 // Terms of the local energy of one ordered pair: u, V, u'/r (the gradient of
 // ln psi is sum u'/r d) and u'' + 2u'/r (the Laplacian term), zero beyond L/2.
 // u' = -5 c5 (r^-6 - (L-r)^-6), u'' = 30 c5 (r^-7 + (L-r)^-7).
@@ -383,14 +485,14 @@ __device__ __forceinline__ void pair_energy(const KParams &p, double r2, ETerms 
     const double ea = fma(az::beta_rm2, r2, -(az::alpha_rm * r));
     double rep = 0.0;
     if (ea > az::rep_min)
-        rep = az::A * exp_neg(ea);
+        rep = az::A * exp_neg(p, ea);
     const double y = az::rm2 * ri2;
     const double y2 = y * y;
     const double disp = y2 * y * fma(y, fma(y, az::C10, az::C8), az::C6);
     double F = 1.0;
     if (r < az::Drm) {
         const double q = fma(az::Drm, ri, -1.0);
-        F = exp_neg(-(q * q));
+        F = exp_neg(p, -(q * q));
     }
     const double vv = az::eps * fma(-F, disp, rep);
     const double dur = du * ri;

@@ -539,6 +539,9 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
     // (small N): in the large-walker kernels their registers would crowd the
     // eight-chunk form, which then spills.
     constexpr bool kFewChunkModes = NT <= 128;
+    // atoms per group of the FP64 row-sum accept pass (1: no grouping); more
+    // than these make the kernels spill
+    constexpr int kAcceptGroup = NT == 256 ? 4 : NT == 512 ? 2 : 1;
     const int nchunks = (n + NT - 1) / NT;
     const int lane_mode = n == kRowsPerLane * NT ? kRowsPerLane
                           : nchunks <= 1       ? 1
@@ -728,7 +731,8 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                                 const T r2n = dist2(p, nx, ny, nz, xi, yi, zi);
                                 const T rio = inv_sqrt(r2o), rin = inv_sqrt(r2n);
                                 const T uo = pair_u_ri(p, r2o, rio), un = pair_u_ri(p, r2n, rin);
-                                const T vo = pair_v_ri(p, r2o, rio), vn = pair_v_ri(p, r2n, rin);
+                                T vo, vn;
+                                pair_v_ri2(p, r2o, rio, r2n, rin, vo, vn);
                                 const bool other = live && i != s;
                                 rr[q] += other ? (double)un - (double)uo : 0.0;
                                 dvl += other ? (double)vn - (double)vo : 0.0;
@@ -839,6 +843,37 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                         auto accept_pass = [&](auto mode_c) {
                             constexpr int MODE = decltype(mode_c)::value;
                             constexpr int CH = MODE == 0 ? kRowsPerLane : MODE;
+                            if constexpr (sizeof(T) == 8 && kAcceptGroup > 1 && MODE == kRowsPerLane && CH % kAcceptGroup == 0) {
+                                // FP64, every lane owning CH atoms: kAcceptGroup atoms at
+                                // a time, their branch-free arithmetic interleaved around
+                                // the exponentials' branches (same values, same order)
+#pragma unroll
+                                for (int j0 = 0; j0 < CH; j0 += kAcceptGroup) {
+                                    double r2o[kAcceptGroup], uo[kAcceptGroup];
+                                    VPair vp[kAcceptGroup];
+#pragma unroll
+                                    for (int g = 0; g < kAcceptGroup; ++g) {
+                                        const int i = tid + (j0 + g) * NT;
+                                        r2o[g] = dist2(p, ox, oy, oz, sx[i], sy[i], sz[i]);
+                                        const double rio = inv_sqrt(r2o[g]);
+                                        uo[g] = pair_u_ri(p, r2o[g], rio);
+                                        vp_pre(p, r2o[g], rio, r2n_[j0 + g], rin_[j0 + g], vp[g]);
+                                    }
+#pragma unroll
+                                    for (int g = 0; g < kAcceptGroup; ++g)
+                                        vp_exp(p, vp[g]);
+#pragma unroll
+                                    for (int g = 0; g < kAcceptGroup; ++g) {
+                                        const int i = tid + (j0 + g) * NT;
+                                        double vo, vn;
+                                        vp_post(vp[g], vo, vn);
+                                        const bool other = i != s;
+                                        ru[i] += keep_or_tiny(other, (double)un_[j0 + g] - uo[g]);
+                                        dvl += keep_or_tiny(other, vn - vo);
+                                    }
+                                }
+                                return;
+                            }
 #pragma unroll
                             for (int jj = 0; jj < CH; ++jj) {
                                 const int i = tid + jj * NT;
@@ -850,8 +885,8 @@ __device__ __forceinline__ void sweep_walker(const KParams &p, uint32_t wid, T *
                                                        : dist2(p, ox, oy, oz, sx[ic], sy[ic], sz[ic]);
                                     const T rio = inv_sqrt(r2o);
                                     const T uo = pair_u_ri(p, r2o, rio);
-                                    const T vo = pair_v_ri(p, r2o, rio);
-                                    const T vn = pair_v_ri(p, r2n_[jj], rin_[jj]);
+                                    T vo, vn;
+                                    pair_v_ri2(p, r2o, rio, r2n_[jj], rin_[jj], vo, vn);
                                     const bool other = live && (i != s);
                                     const double dr = keep_or_tiny(other, (double)un_[jj] - (double)uo);
                                     if constexpr (kReg && kCacheRow) {
