@@ -268,6 +268,47 @@ __device__ __forceinline__ void pair_uv(const KParams &p, double r2, double &u, 
     v = in ? vv : 0.0;
 }
 
+// FP64: pair_uv at two distances (a moved atom's old and new position against
+// one partner), each bitwise equal to pair_uv; the exponentials of both are
+// formed in shared branches so that their Horner chains interleave.
+__device__ __forceinline__ void pair_uv2(const KParams &p, double r2a, double r2b, double &ua, double &va,
+                                         double &ub, double &vb)
+{
+    const double ria = rsq_nr(r2a), rib = rsq_nr(r2b);
+    const double ra = r2a * ria, rb = r2b * rib;
+    const double rpa = rcp_nr(p.L - ra), rpb = rcp_nr(p.L - rb);
+    const double ria2 = ria * ria, rpa2 = rpa * rpa, rib2 = rib * rib, rpb2 = rpb * rpb;
+    const double uua = fma(p.c5, fma(ria2 * ria2, ria, rpa2 * rpa2 * rpa), p.u0);
+    const double uub = fma(p.c5, fma(rib2 * rib2, rib, rpb2 * rpb2 * rpb), p.u0);
+    const double eaa = fma(az::beta_rm2, r2a, -(az::alpha_rm * ra));
+    const double eab = fma(az::beta_rm2, r2b, -(az::alpha_rm * rb));
+    const bool ka = eaa > az::rep_min, kb = eab > az::rep_min;
+    double repa = 0.0, repb = 0.0;
+    if (ka || kb) {
+        const double xa = exp_neg(p, eaa), xb = exp_neg(p, eab);
+        repa = ka ? az::A * xa : 0.0;
+        repb = kb ? az::A * xb : 0.0;
+    }
+    const double ya = az::rm2 * ria2, yb = az::rm2 * rib2;
+    const double ya2 = ya * ya, yb2 = yb * yb;
+    const double dispa = ya2 * ya * fma(ya, fma(ya, az::C10, az::C8), az::C6);
+    const double dispb = yb2 * yb * fma(yb, fma(yb, az::C10, az::C8), az::C6);
+    const bool da = ra < az::Drm, db = rb < az::Drm;
+    double Fa = 1.0, Fb = 1.0;
+    if (da || db) {
+        const double qa = fma(az::Drm, ria, -1.0), qb = fma(az::Drm, rib, -1.0);
+        const double xa = exp_neg(p, -(qa * qa)), xb = exp_neg(p, -(qb * qb));
+        Fa = da ? xa : 1.0;
+        Fb = db ? xb : 1.0;
+    }
+    const double vva = az::eps * fma(-Fa, dispa, repa), vvb = az::eps * fma(-Fb, dispb, repb);
+    const bool ina = r2a <= p.h2, inb = r2b <= p.h2;
+    ua = ina ? uua : 0.0;
+    va = ina ? vva : 0.0;
+    ub = inb ? uub : 0.0;
+    vb = inb ? vvb : 0.0;
+}
+
 // Whether a pair at squared distance r2 is inside the (inclusive) cutoff.
 __device__ __forceinline__ bool pair_inside(const KParams &p, double r2) { return r2 <= p.h2; }
 __device__ __forceinline__ bool pair_inside(const KParams &p, float r2) { return r2 <= p.h2f; }
@@ -430,6 +471,13 @@ __device__ __forceinline__ void pair_uv(const KParams &p, float r2, float &u, fl
     const bool in = r2 <= p.h2f;
     u = in ? uu : 0.0f;
     v = in ? vv : 0.0f;
+}
+
+__device__ __forceinline__ void pair_uv2(const KParams &p, float r2a, float r2b, float &ua, float &va, float &ub,
+                                         float &vb)
+{
+    pair_uv(p, r2a, ua, va);
+    pair_uv(p, r2b, ub, vb);
 }
 
 __device__ __forceinline__ float pair_u_ri(const KParams &p, float r2, float ri)

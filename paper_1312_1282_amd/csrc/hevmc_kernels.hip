@@ -289,8 +289,7 @@ __device__ __forceinline__ void move_partial(const KParams &p, const T *sx, cons
         const T r2o = ax * ax + ay * ay + az_ * az_;
         const T r2n = bx * bx + by * by + bz * bz;
         T uo, vo, un, vn;
-        pair_uv(p, r2o, uo, vo);
-        pair_uv(p, r2n, un, vn);
+        pair_uv2(p, r2o, r2n, uo, vo, un, vn);
         const bool self = (i == s);
         du += self ? 0.0 : (double)(un - uo);
         dv += self ? 0.0 : (double)(vn - vo);
@@ -1887,8 +1886,7 @@ __global__ __launch_bounds__(NT) void k_sweep_coop(KParams p, CoopArgs c, T *__r
                     const T r2o = dist2(p, ox, oy, oz, xi, yi, zi);
                     const T r2n = dist2(p, nx, ny, nz, xi, yi, zi);
                     T uo, vo, un, vn;
-                    pair_uv(p, r2o, uo, vo);
-                    pair_uv(p, r2n, un, vn);
+                    pair_uv2(p, r2o, r2n, uo, vo, un, vn);
                     const bool self = (i0 + q == s);
                     du += self ? 0.0 : (double)(un - uo);
                     dv += self ? 0.0 : (double)(vn - vo);
