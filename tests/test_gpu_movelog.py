@@ -105,6 +105,7 @@ def compare_fp64(g, o, rows_form):
     (256, 3, 128, 100, abi.VARIANT_PLAIN),
     (300, 2, 256, 60, abi.VARIANT_ROWS),    # ragged: some lanes own fewer atoms
     (1024, 2, 128, 60, abi.VARIANT_ROWS),   # eight atoms per lane (dense passes)
+    (4096, 1, 512, 2, abi.VARIANT_ROWS),    # eight atoms per lane at 512 threads: accept pass in pairs
 ])
 def test_every_move_follows_the_oracle_fp64(n, W, threads, sweeps, variant):
     p = abi.make_params(n, W, density=RHO, b=B, step_sigma=STEP, seed=31, threads=threads, variant=variant)
