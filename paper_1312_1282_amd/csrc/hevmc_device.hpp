@@ -360,44 +360,14 @@ __device__ __forceinline__ double pair_v_ri(const KParams &p, double r2, double 
 }
 
 // FP64: V at two distances (a moved atom's old and new position against one
-// partner), each bitwise equal to pair_v_ri.  An exponential is formed for
-// both distances when either needs it (the other's value is discarded), so
-// the two dependent Horner chains run interleaved in one branch instead of
-// one after the other in two.
-__device__ __forceinline__ void pair_v_ri2(const KParams &p, double r2a, double ria, double r2b, double rib,
-                                           double &va, double &vb)
-{
-    const double ra = r2a * ria, rb = r2b * rib;
-    const double eaa = fma(az::beta_rm2, r2a, -(az::alpha_rm * ra));
-    const double eab = fma(az::beta_rm2, r2b, -(az::alpha_rm * rb));
-    const bool ka = eaa > az::rep_min, kb = eab > az::rep_min;
-    double repa = 0.0, repb = 0.0;
-    if (ka || kb) {
-        const double xa = exp_neg(p, eaa), xb = exp_neg(p, eab);
-        repa = ka ? az::A * xa : 0.0;
-        repb = kb ? az::A * xb : 0.0;
-    }
-    const double ya = az::rm2 * (ria * ria), yb = az::rm2 * (rib * rib);
-    const double ya2 = ya * ya, yb2 = yb * yb;
-    const double dispa = ya2 * ya * fma(ya, fma(ya, az::C10, az::C8), az::C6);
-    const double dispb = yb2 * yb * fma(yb, fma(yb, az::C10, az::C8), az::C6);
-    const bool da = ra < az::Drm, db = rb < az::Drm;
-    double Fa = 1.0, Fb = 1.0;
-    if (da || db) {
-        const double qa = fma(az::Drm, ria, -1.0), qb = fma(az::Drm, rib, -1.0);
-        const double xa = exp_neg(p, -(qa * qa)), xb = exp_neg(p, -(qb * qb));
-        Fa = da ? xa : 1.0;
-        Fb = db ? xb : 1.0;
-    }
-    va = keep_or_tiny(r2a <= p.h2, az::eps * fma(-Fa, dispa, repa));
-    vb = keep_or_tiny(r2b <= p.h2, az::eps * fma(-Fb, dispb, repb));
-}
-
-// pair_v_ri2 in three phases, for callers that hold several such pairs:
-// vp_pre forms everything but the exponentials, vp_exp the exponentials
-// (the two branches), vp_post the two values.  Running every pair's vp_pre,
-// then every vp_exp, then every vp_post interleaves the pairs' arithmetic
-// outside the branches.  The values are bitwise those of pair_v_ri2.
+// partner), each bitwise equal to pair_v_ri, in three phases: vp_pre forms
+// everything but the exponentials, vp_exp the exponentials, vp_post the two
+// values.  An exponential is formed for both distances when either needs it
+// (the other's value is discarded), so the two dependent Horner chains run
+// interleaved in one branch instead of one after the other in two.  A caller
+// holding several such pairs runs every pair's vp_pre, then every vp_exp, then
+// every vp_post, so that the pairs' arithmetic also interleaves outside the
+// branches; pair_v_ri2 is the three phases for one pair.
 struct VPair {
     double disa, disb, eaa, eab, qa, qb, repa, repb, Fa, Fb;
     bool ka, kb, da, db, ina, inb;
@@ -444,6 +414,15 @@ __device__ __forceinline__ void vp_post(const VPair &v, double &va, double &vb)
 {
     va = keep_or_tiny(v.ina, az::eps * fma(-v.Fa, v.disa, v.repa));
     vb = keep_or_tiny(v.inb, az::eps * fma(-v.Fb, v.disb, v.repb));
+}
+
+__device__ __forceinline__ void pair_v_ri2(const KParams &p, double r2a, double ria, double r2b, double rib,
+                                           double &va, double &vb)
+{
+    VPair v;
+    vp_pre(p, r2a, ria, r2b, rib, v);
+    vp_exp(p, v);
+    vp_post(v, va, vb);
 }
 
 // FP32 form: same terms in single precision with the hardware reciprocal,
