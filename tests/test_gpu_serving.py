@@ -121,27 +121,29 @@ def test_replicated_server_alone_and_in_mix_and_energy():
 def test_freed_slots_and_admission_during_flight_keep_results():
     """Continuous batching proper: one request per class at a time, so later
     requests of a class wait for an earlier one to retire and take its freed
-    slots, and are admitted while the other class has a launch in flight (its
-    walkers are large enough, N=1024 and 256 of them, that its launches take
-    milliseconds and follow each other back to back); staggered real-time
-    arrivals.  Every result equals the same request served alone, bit for
-    bit."""
-    mk = lambda: [_req(0, 108, 64, abi.FP64, 0.0200, 2.8, 41), _req(1, 1024, 256, abi.FP32, 0.0215, 3.0, 42),
-                  _req(2, 108, 64, abi.FP64, 0.0230, 3.1, 43), _req(3, 1024, 192, abi.FP32, 0.0205, 2.9, 44),
+    slots, and the small class's requests are admitted while the large class
+    has a launch in flight: the large request (N=2048 FP32, 256 walkers) comes
+    first and its launches take about 10 ms each, and the first small one
+    (N=108 FP64) arrives 2 ms after it.  Staggered real-time arrivals.  Every
+    result equals the same request served alone, bit for bit."""
+    mk = lambda: [_req(0, 2048, 256, abi.FP32, 0.0215, 3.0, 42), _req(1, 108, 64, abi.FP64, 0.0200, 2.8, 41),
+                  _req(2, 108, 64, abi.FP64, 0.0230, 3.1, 43), _req(3, 2048, 192, abi.FP32, 0.0205, 2.9, 44),
                   _req(4, 108, 32, abi.FP64, 0.0219, 2.94, 45)]
     kw = dict(target_se=4e-3, equil=20, check_every=10, min_samples=2, quantum=5, max_requests_per_class=1,
               slots_per_class=256)
     reqs = mk()
     for k, r in enumerate(reqs):
-        r.arrival = 0.02 * k
+        r.arrival = 0.002 * k
     mix = serving.Server(**kw).run(reqs, realtime=True)
     for r in mix:
         assert r.done is not None and r.rejected is None and r.failed is None, r.rid
     # later requests of a class reuse the slots of the one before them
-    assert mix[2].slot0 == mix[0].slot0 and mix[2].admitted >= mix[0].done
+    assert mix[2].slot0 == mix[1].slot0 and mix[2].admitted >= mix[1].done
     assert mix[4].slot0 == mix[2].slot0 and mix[4].admitted >= mix[2].done
-    assert mix[3].slot0 == mix[1].slot0 and mix[3].admitted >= mix[1].done
-    assert any(r.admitted_during_flight for r in mix[1:])
+    assert mix[3].slot0 == mix[0].slot0 and mix[3].admitted >= mix[0].done
+    # request 1 arrives 2 ms after the large request 0 was admitted and
+    # launched, into a launch of about 10 ms
+    assert any(mix[k].admitted_during_flight for k in (1, 2, 4)), [(r.rid, r.admitted, r.done) for r in mix]
     for k in range(5):
         alone = serving.Server(**{**kw, "max_requests_per_class": 16, "slots_per_class": 8192}).run(
             [mk()[k]], realtime=False)[0]
