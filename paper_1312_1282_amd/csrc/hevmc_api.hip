@@ -355,8 +355,6 @@ void make_kparams(const hevmc_params *p, KParams &k)
         k.vc8 = (float)az::eC8;
         k.vc10 = (float)az::eC10;
     }
-    for (int j = 0; j < 10; ++j)
-        k.ex[j] = kExpTaylor[j];
     k.sorted = 0;
     k.gr_bins = 0;
     k.gr = nullptr;

@@ -31,12 +31,6 @@ struct KParams {
     // F = 2^-((vd / r - vs)^2) for r < vdr = D r_m; dispersion coefficients
     // vc6, vc8, vc10 on powers of 1/r^2 (eps and r_m folded in)
     float vb, va, vl, vd, vs, vdr, vc6, vc8, vc10;
-    // Taylor coefficients 1/12!, 1/11!, ..., 1/3! of the FP64 exponential
-    // (exp_neg), copied from kExpTaylor on the host.  As kernel arguments they
-    // sit in scalar registers, where each Horner step takes its coefficient as
-    // the addend of one FMA; compile-time constants would be held in vector
-    // registers and copied before every step.
-    double ex[10];
     int32_t sorted;      // sweep keeps the atoms in LDS in spatial (Morton) order
     int32_t gr_bins;     // bins of the pair histogram accumulated at each sample (0: none)
     uint64_t *gr;        // [W][gr_bins] histogram counts (device), or null
@@ -79,12 +73,23 @@ constexpr double eC10 = eC6 / C6 * C10 * rm2 * rm2;
 constexpr double rep_min = -55.0;
 }  // namespace az
 
-// 1/k! for k = 12, 11, ..., 3: the Taylor coefficients of exp_neg.
-constexpr double kExpTaylor[10] = {
+// 1/k! for k = 12, 11, ..., 3: the Taylor coefficients of exp_neg, in
+// constant memory.  Not declared const, so the compiler cannot fold them into
+// the code: it loads them once into scalar registers, where each Horner step
+// takes its coefficient as the addend of one FMA.  As compile-time constants
+// they would be held in vector registers and copied before every step (the
+// addend of the two-operand FMA form is also its result).
+// (Defined in the kernels' translation unit only; external linkage keeps the
+// optimiser from treating the initial values as the final ones.)
+#ifdef HEVMC_KERNELS_TU
+__constant__ double exp_taylor[10] = {
     2.08767569878680989792e-09, 2.50521083854417187751e-08, 2.75573192239858906526e-07,
     2.75573192239858906526e-06, 2.48015873015873015873e-05, 1.98412698412698412698e-04,
     1.38888888888888888889e-03, 8.33333333333333333333e-03, 4.16666666666666666667e-02,
     1.66666666666666666667e-01};
+#else
+extern __constant__ double exp_taylor[10];
+#endif
 
 // --------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64 products.
@@ -212,16 +217,16 @@ __device__ __forceinline__ double rsq_nr(double x)
 // scaled by 2^k.  For a below about -745 the scaling underflows to zero, the
 // value of e^a in FP64 (a = -inf, the distance-zero pair of an atom with
 // itself, gives NaN, which the callers' masks discard).  The coefficients of
-// degrees 12 .. 3 come from p.ex (= kExpTaylor).
-__device__ __forceinline__ double exp_neg(const KParams &p, double a)
+// degrees 12 .. 3 come from exp_taylor.
+__device__ __forceinline__ double exp_neg(const KParams &, double a)
 {
     const double k = rint(a * 1.4426950408889634);
     double f = fma(-k, 6.93147180369123816490e-01, a);
     f = fma(-k, 1.90821492927058770002e-10, f);
-    double q = p.ex[0];
+    double q = exp_taylor[0];
 #pragma unroll
     for (int j = 1; j < 10; ++j)
-        q = fma(q, f, p.ex[j]);
+        q = fma(q, f, exp_taylor[j]);
     q = fma(q, f, 0.5);
     q = fma(q, f, 1.0);
     q = fma(q, f, 1.0);

@@ -37,6 +37,7 @@
 #include <atomic>
 #include <type_traits>
 
+#define HEVMC_KERNELS_TU 1
 #include "hevmc_device.hpp"
 #include "hevmc_internal.hpp"
 
